@@ -1,0 +1,1234 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of the MAP EGLM-MHD block update.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Written for readability, not
+ * speed: every quantity is computed where the paper defines it, with
+ * temporary arrays instead of fusion, and in the order the equations are
+ * printed.  Build with -O2 -ffp-contract=off and no fast-math.
+ *
+ * Section references are to the paper (Jiang, Fang & Chen, MAP):
+ *   Sec. 2  EGLM-MHD equations (MHD-1..MHD-5), c_h and c_p
+ *   Sec. 3  conservative update (Equ:basic), MMC, LF (Equ:LFFlux,
+ *           limiter1/limiter2, minmod), resistivity, multi-D and dt
+ *   Sec. 4.3 boundary procedure: restriction, reflux, exchange, conservative
+ *           prolongation (Matsumoto's minmod interpolation)
+ *   Sec. 4.5 regrid error estimator
+ *   Sec. 5  error norms
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { RHO = 0, MX = 1, MY = 2, MZ = 3, BX = 4, BY = 5, BZ = 6, EN = 7, PSI = 8 };
+#define NVMAX 9
+
+/* ------------------------------------------------------------------ */
+/* tile geometry                                                       */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int nd;
+    int n[3], g[3], p[3];
+    long s[3];  /* strides of x, y, z in the padded tile */
+    long P;     /* cells per variable in the padded tile */
+    long I;     /* interior cells per variable */
+} geo;
+
+static geo mkgeo(int nd, const int n_in[3])
+{
+    geo G;
+    G.nd = nd;
+    for (int d = 0; d < 3; d++) {
+        G.n[d] = (d < nd) ? n_in[d] : 1;
+        G.g[d] = (d < nd) ? 2 : 0;
+        G.p[d] = G.n[d] + 2 * G.g[d];
+    }
+    G.s[0] = 1;
+    G.s[1] = G.p[0];
+    G.s[2] = (long)G.p[0] * G.p[1];
+    G.P = (long)G.p[0] * G.p[1] * G.p[2];
+    G.I = (long)G.n[0] * G.n[1] * G.n[2];
+    return G;
+}
+
+static long at(const geo *G, int x, int y, int z)
+{
+    return ((long)(z + G->g[2]) * G->p[1] + (y + G->g[1])) * G->p[0] + (x + G->g[0]);
+}
+
+static long interior_index(const geo *G, int x, int y, int z)
+{
+    return ((long)z * G->n[1] + y) * G->n[0] + x;
+}
+
+/* ------------------------------------------------------------------ */
+/* pointwise physics                                                   */
+/* ------------------------------------------------------------------ */
+int orc_nvar(const orc_params *p) { return p->physics == ORC_MHD ? 9 : 1; }
+
+/* p = (gamma-1)(e - rho v^2/2 - B^2/2)   (Sec. 2, below MHD-04) */
+double orc_pressure(const orc_params *p, const double *u)
+{
+    double ir = 1.0 / u[RHO];
+    double vx = u[MX] * ir, vy = u[MY] * ir, vz = u[MZ] * ir;
+    double ke = 0.5 * (u[MX] * vx + u[MY] * vy + u[MZ] * vz);
+    double me = 0.5 * (u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ]);
+    return (p->gamma - 1.0) * (u[EN] - ke - me);
+}
+
+/* flux of the EGLM-MHD system in direction `dim` (MHD-1..MHD-5):
+ * mass m_d; momentum m_j v_d - B_j B_d + delta_jd (p + B^2/2);
+ * induction B_j v_d - B_d v_j plus psi on the normal component;
+ * energy (e + p + B^2/2) v_d - B_d (v.B); psi: c_h^2 B_d. */
+void orc_flux(const orc_params *p, const double *u, int d, double ch, double *f)
+{
+    if (p->physics == ORC_SCALAR) {
+        f[0] = p->adv[d] * u[0];
+        return;
+    }
+    double ir = 1.0 / u[RHO];
+    double v[3] = {u[MX] * ir, u[MY] * ir, u[MZ] * ir};
+    const double *B = u + BX;
+    double ke = 0.5 * (u[MX] * v[0] + u[MY] * v[1] + u[MZ] * v[2]);
+    double me = 0.5 * (B[0] * B[0] + B[1] * B[1] + B[2] * B[2]);
+    double pr = (p->gamma - 1.0) * (u[EN] - ke - me);
+    double pt = pr + me;
+    double vd = v[d], Bd = B[d];
+    double vb = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
+    f[RHO] = u[MX + d];
+    for (int j = 0; j < 3; j++)
+        f[MX + j] = u[MX + j] * vd - B[j] * Bd;
+    f[MX + d] = f[MX + d] + pt;
+    for (int j = 0; j < 3; j++)
+        f[BX + j] = B[j] * vd - Bd * v[j];
+    f[BX + d] = u[PSI];
+    f[EN] = (u[EN] + pt) * vd - Bd * vb;
+    f[PSI] = ch * ch * Bd;
+}
+
+/* |v_d| + fast magnetosonic speed along d (the "local maximum eigenvalue"
+ * of the MHD part; the GLM speed c_h is handled separately). */
+double orc_speed(const orc_params *p, const double *u, int d)
+{
+    if (p->physics == ORC_SCALAR)
+        return fabs(p->adv[d]);
+    double ir = 1.0 / u[RHO];
+    double pr = orc_pressure(p, u);
+    double a2 = p->gamma * pr * ir;
+    double bb = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
+    double b2 = bb * ir;
+    double s = a2 + b2;
+    double disc = s * s - 4.0 * a2 * (u[BX + d] * u[BX + d]) * ir;
+    if (disc < 0.0)
+        disc = 0.0;
+    double cf2 = 0.5 * (s + sqrt(disc));
+    if (cf2 < 0.0)
+        cf2 = 0.0;
+    return fabs(u[MX + d] * ir) + sqrt(cf2);
+}
+
+static double sgn(double x) { return (double)((x > 0.0) - (x < 0.0)); }
+
+/* minmod(a,b) = sgn(a) max(0, min(|a|, sgn(a) b))   (eq. minmod)
+ * van Leer:      (ab + |ab|)/(a + b)
+ * literal flux limiter of Sec. 3.1 in ratio-free form: phi(a/b) b. */
+double orc_limiter(int kind, double a, double b)
+{
+    if (kind == ORC_MINMOD) {
+        double s = sgn(a);
+        double m = fabs(a);
+        double t = s * b;
+        if (t < m)
+            m = t;
+        if (m < 0.0)
+            m = 0.0;
+        return s * m;
+    }
+    if (kind == ORC_VANLEER) {
+        double ab = a * b;
+        if (ab <= 0.0)
+            return 0.0;
+        return (ab + fabs(ab)) / (a + b);
+    }
+    /* ORC_PAPER_PHI: phi(r) = r for |r| <= 1, 1 otherwise, r = a/b */
+    return (fabs(a) <= fabs(b)) ? a : b;
+}
+
+static int admissible(const orc_params *p, const double *u)
+{
+    if (p->physics == ORC_SCALAR)
+        return 1;
+    if (!(u[RHO] > 0.0))
+        return 0;
+    return orc_pressure(p, u) > 0.0;
+}
+
+/* the GLM pair (B_d, psi) is transported at speed c_h */
+static int glm_component(const orc_params *p, int k, int d)
+{
+    return p->physics == ORC_MHD && (k == BX + d || k == PSI);
+}
+
+/* primitive (rho, v, B, p, psi) -> conserved (rho, rho v, B, e, psi);
+ * w is [9][ncell].  e = p/(gamma-1) + rho v^2/2 + B^2/2 (Sec. 2). */
+void orc_prim_to_cons(const orc_params *p, double *w, long nc)
+{
+    if (p->physics == ORC_SCALAR)
+        return;
+    for (long c = 0; c < nc; c++) {
+        double r = w[RHO * nc + c];
+        double vx = w[MX * nc + c], vy = w[MY * nc + c], vz = w[MZ * nc + c];
+        double bx = w[BX * nc + c], by = w[BY * nc + c], bz = w[BZ * nc + c];
+        double pr = w[EN * nc + c];
+        double e = pr / (p->gamma - 1.0) + 0.5 * r * (vx * vx + vy * vy + vz * vz)
+                   + 0.5 * (bx * bx + by * by + bz * bz);
+        w[MX * nc + c] = r * vx;
+        w[MY * nc + c] = r * vy;
+        w[MZ * nc + c] = r * vz;
+        w[EN * nc + c] = e;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* one padded tile                                                     */
+/* ------------------------------------------------------------------ */
+static void load(const double *u, long P, int nv, long c, double *out)
+{
+    for (int k = 0; k < nv; k++)
+        out[k] = u[k * P + c];
+}
+
+/* the (n+2)^d region E: one ring outside the interior */
+static void e_range(const geo *G, int lo[3], int hi[3])
+{
+    for (int d = 0; d < 3; d++) {
+        lo[d] = (d < G->nd) ? -1 : 0;
+        hi[d] = (d < G->nd) ? G->n[d] + 1 : G->n[d];
+    }
+}
+
+/* LF predictor (limiter1 + the half-step formula): per cell of E,
+ * slopes from the old-time differences, fall-back to zero slopes if a face
+ * state is not admissible, then u~ = u - dt/(2dx) sum_d [f(u+D/2) - f(u-D/2)]. */
+static void lf_predict(const orc_params *p, const geo *G, const double *u,
+                       const double hdt[3], double ch, double *ut, double *sl,
+                       long *cnt)
+{
+    int nv = orc_nvar(p), nd = G->nd;
+    long P = G->P;
+    int lo[3], hi[3];
+    e_range(G, lo, hi);
+    for (int z = lo[2]; z < hi[2]; z++)
+        for (int y = lo[1]; y < hi[1]; y++)
+            for (int x = lo[0]; x < hi[0]; x++) {
+                long c = at(G, x, y, z);
+                double uc[NVMAX], s[3][NVMAX];
+                load(u, P, nv, c, uc);
+                for (int d = 0; d < nd; d++)
+                    for (int k = 0; k < nv; k++) {
+                        double a = uc[k] - u[k * P + c - G->s[d]];
+                        double b = u[k * P + c + G->s[d]] - uc[k];
+                        s[d][k] = orc_limiter(p->limiter, a, b);
+                    }
+                int ok = 1;
+                for (int d = 0; d < nd; d++) {
+                    double up[NVMAX], um[NVMAX];
+                    for (int k = 0; k < nv; k++) {
+                        up[k] = uc[k] + 0.5 * s[d][k];
+                        um[k] = uc[k] - 0.5 * s[d][k];
+                    }
+                    if (!admissible(p, up) || !admissible(p, um))
+                        ok = 0;
+                }
+                if (!ok) {
+                    memset(s, 0, sizeof(s));
+                    cnt[0]++;
+                }
+                double acc[NVMAX] = {0};
+                for (int d = 0; d < nd; d++) {
+                    double up[NVMAX], um[NVMAX], fp[NVMAX], fm[NVMAX];
+                    for (int k = 0; k < nv; k++) {
+                        up[k] = uc[k] + 0.5 * s[d][k];
+                        um[k] = uc[k] - 0.5 * s[d][k];
+                    }
+                    orc_flux(p, up, d, ch, fp);
+                    orc_flux(p, um, d, ch, fm);
+                    for (int k = 0; k < nv; k++)
+                        acc[k] += hdt[d] * (fp[k] - fm[k]);
+                }
+                for (int k = 0; k < nv; k++) {
+                    ut[k * P + c] = uc[k] - acc[k];
+                    for (int d = 0; d < nd; d++)
+                        sl[((long)d * nv + k) * P + c] = s[d][k];
+                }
+            }
+}
+
+/* LF corrector fluxes (limiter2 + Equ:LFFlux) on every face of dimension d
+ * that bounds an interior cell; the face c+1/2 is stored at index c. */
+static void lf_faces(const orc_params *p, const geo *G, const double *ut,
+                     const double *sl, int d, double ch, double *fh, long *cnt)
+{
+    int nv = orc_nvar(p);
+    long P = G->P;
+    int lo[3] = {0, 0, 0}, hi[3] = {G->n[0], G->n[1], G->n[2]};
+    lo[d] = -1;
+    hi[d] = G->n[d];
+    for (int z = lo[2]; z < hi[2]; z++)
+        for (int y = lo[1]; y < hi[1]; y++)
+            for (int x = lo[0]; x < hi[0]; x++) {
+                long c = at(G, x, y, z), cn = c + G->s[d];
+                double L[NVMAX], R[NVMAX], FL[NVMAX], FR[NVMAX];
+                for (int k = 0; k < nv; k++) {
+                    L[k] = ut[k * P + c] + 0.5 * sl[((long)d * nv + k) * P + c];
+                    R[k] = ut[k * P + cn] - 0.5 * sl[((long)d * nv + k) * P + cn];
+                }
+                if (!admissible(p, L)) {
+                    load(ut, P, nv, c, L);
+                    cnt[1]++;
+                }
+                if (!admissible(p, R)) {
+                    load(ut, P, nv, cn, R);
+                    cnt[1]++;
+                }
+                orc_flux(p, L, d, ch, FL);
+                orc_flux(p, R, d, ch, FR);
+                double aL = orc_speed(p, L, d), aR = orc_speed(p, R, d);
+                double a = aL > aR ? aL : aR;
+                for (int k = 0; k < nv; k++) {
+                    double al = glm_component(p, k, d) ? ch : a;
+                    fh[k * P + c] = 0.5 * (FL[k] + FR[k]) - 0.5 * al * (R[k] - L[k]);
+                }
+            }
+}
+
+/* MMC (Sec. 3.1): Lax-Friedrichs splitting f+- = (f +- alpha u)/2 with the
+ * global alpha (c_h on the GLM pair), predictor with h = f+_i + f-_{i+1},
+ * and the flux-limited correction with g+ and g- built from u~. */
+static void mmc_fluxes(const orc_params *p, const geo *G, const double *u,
+                       const double dtdx[3], const orc_dtrec *dt, double *fh[3])
+{
+    int nv = orc_nvar(p), nd = G->nd;
+    long P = G->P;
+    double *fp[3], *fm[3], *ftp[3], *ftm[3];
+    double *ut = calloc((size_t)nv * P, sizeof(double));
+    for (int d = 0; d < nd; d++) {
+        fp[d] = calloc((size_t)nv * P, sizeof(double));
+        fm[d] = calloc((size_t)nv * P, sizeof(double));
+        ftp[d] = calloc((size_t)nv * P, sizeof(double));
+        ftm[d] = calloc((size_t)nv * P, sizeof(double));
+    }
+    /* split fluxes of u on the whole padded tile */
+    for (int z = -G->g[2]; z < G->n[2] + G->g[2]; z++)
+        for (int y = -G->g[1]; y < G->n[1] + G->g[1]; y++)
+            for (int x = -G->g[0]; x < G->n[0] + G->g[0]; x++) {
+                long c = at(G, x, y, z);
+                double uc[NVMAX], F[NVMAX];
+                load(u, P, nv, c, uc);
+                for (int d = 0; d < nd; d++) {
+                    orc_flux(p, uc, d, dt->ch, F);
+                    for (int k = 0; k < nv; k++) {
+                        double al = glm_component(p, k, d) ? dt->ch : dt->alpha;
+                        fp[d][k * P + c] = 0.5 * (F[k] + al * uc[k]);
+                        fm[d][k * P + c] = 0.5 * (F[k] - al * uc[k]);
+                    }
+                }
+            }
+    /* predictor u~ on E */
+    int lo[3], hi[3];
+    e_range(G, lo, hi);
+    for (int z = lo[2]; z < hi[2]; z++)
+        for (int y = lo[1]; y < hi[1]; y++)
+            for (int x = lo[0]; x < hi[0]; x++) {
+                long c = at(G, x, y, z);
+                for (int k = 0; k < nv; k++) {
+                    double acc = 0.0;
+                    for (int d = 0; d < nd; d++) {
+                        long s = G->s[d];
+                        double hp = fp[d][k * P + c] + fm[d][k * P + c + s];
+                        double hm = fp[d][k * P + c - s] + fm[d][k * P + c];
+                        acc += dtdx[d] * (hp - hm);
+                    }
+                    ut[k * P + c] = u[k * P + c] - acc;
+                }
+                double uc[NVMAX], F[NVMAX];
+                load(ut, P, nv, c, uc);
+                for (int d = 0; d < nd; d++) {
+                    orc_flux(p, uc, d, dt->ch, F);
+                    for (int k = 0; k < nv; k++) {
+                        double al = glm_component(p, k, d) ? dt->ch : dt->alpha;
+                        ftp[d][k * P + c] = 0.5 * (F[k] + al * uc[k]);
+                        ftm[d][k * P + c] = 0.5 * (F[k] - al * uc[k]);
+                    }
+                }
+            }
+    /* limited fluxes on the faces bounding interior cells */
+    for (int d = 0; d < nd; d++) {
+        int flo[3] = {0, 0, 0}, fhi[3] = {G->n[0], G->n[1], G->n[2]};
+        flo[d] = -1;
+        fhi[d] = G->n[d];
+        long s = G->s[d];
+        for (int z = flo[2]; z < fhi[2]; z++)
+            for (int y = flo[1]; y < fhi[1]; y++)
+                for (int x = flo[0]; x < fhi[0]; x++) {
+                    long c = at(G, x, y, z);
+                    for (int k = 0; k < nv; k++) {
+                        long o = (long)k * P;
+                        double h = fp[d][o + c] + fm[d][o + c + s];
+                        double gp_m = ftp[d][o + c] - fp[d][o + c - s];     /* g+ at i-1/2 */
+                        double gp_p = ftp[d][o + c + s] - fp[d][o + c];     /* g+ at i+1/2 */
+                        double gm_p = fm[d][o + c + s] - ftm[d][o + c];     /* g- at i+1/2 */
+                        double gm_pp = fm[d][o + c + 2 * s] - ftm[d][o + c + s]; /* g- at i+3/2 */
+                        fh[d][o + c] = h + 0.5 * (orc_limiter(p->limiter, gp_m, gp_p)
+                                                  - orc_limiter(p->limiter, gm_pp, gm_p));
+                    }
+                }
+    }
+    free(ut);
+    for (int d = 0; d < nd; d++) {
+        free(fp[d]);
+        free(fm[d]);
+        free(ftp[d]);
+        free(ftm[d]);
+    }
+}
+
+/* central difference along d of array a (stride per variable implied) */
+static double cdiff(const double *a, long c, long s, double inv2dx)
+{
+    return (a[c + s] - a[c - s]) * inv2dx;
+}
+
+void orc_eglm_source(const orc_params *p, const double dx[3], const double *u,
+                     const int n_in[3], double *out)
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int nv = orc_nvar(p);
+    long P = G.P;
+    memset(out, 0, sizeof(double) * nv * G.I);
+    if (p->physics != ORC_MHD)
+        return;
+    double inv2dx[3];
+    for (int d = 0; d < G.nd; d++)
+        inv2dx[d] = 0.5 / dx[d];
+    for (int z = 0; z < G.n[2]; z++)
+        for (int y = 0; y < G.n[1]; y++)
+            for (int x = 0; x < G.n[0]; x++) {
+                long c = at(&G, x, y, z), ic = interior_index(&G, x, y, z);
+                double divb = 0.0, bgp = 0.0;
+                for (int d = 0; d < G.nd; d++)
+                    divb += cdiff(u + (BX + d) * P, c, G.s[d], inv2dx[d]);
+                for (int d = 0; d < G.nd; d++)
+                    bgp += u[(BX + d) * P + c] * cdiff(u + PSI * P, c, G.s[d], inv2dx[d]);
+                for (int j = 0; j < 3; j++)
+                    out[(MX + j) * G.I + ic] = -(divb * u[(BX + j) * P + c]);
+                out[EN * G.I + ic] = -bgp;
+            }
+}
+
+void orc_resistive(const orc_params *p, const double dx[3], const double *u,
+                   const int n_in[3], double *out)
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int nv = orc_nvar(p), nd = G.nd;
+    long P = G.P;
+    memset(out, 0, sizeof(double) * nv * G.I);
+    if (p->physics != ORC_MHD)
+        return;
+    double h[3];
+    for (int d = 0; d < nd; d++)
+        h[d] = 0.5 / dx[d];
+    const double *Bx = u + BX * P, *By = u + BY * P, *Bz = u + BZ * P;
+    double *J = calloc((size_t)3 * P, sizeof(double));  /* eta J */
+    double *Q = calloc((size_t)3 * P, sizeof(double));  /* eta (J x B) rows of R_e */
+    int lo[3], hi[3];
+    e_range(&G, lo, hi);
+    double eta = p->eta;
+    /* J = curl B by central differences; z-derivatives vanish in 2-D */
+    for (int z = lo[2]; z < hi[2]; z++)
+        for (int y = lo[1]; y < hi[1]; y++)
+            for (int x = lo[0]; x < hi[0]; x++) {
+                long c = at(&G, x, y, z);
+                double jx, jy, jz;
+                if (nd == 3) {
+                    jx = cdiff(Bz, c, G.s[1], h[1]) - cdiff(By, c, G.s[2], h[2]);
+                    jy = cdiff(Bx, c, G.s[2], h[2]) - cdiff(Bz, c, G.s[0], h[0]);
+                } else {
+                    jx = cdiff(Bz, c, G.s[1], h[1]);
+                    jy = -cdiff(Bz, c, G.s[0], h[0]);
+                }
+                jz = cdiff(By, c, G.s[0], h[0]) - cdiff(Bx, c, G.s[1], h[1]);
+                J[0 * P + c] = eta * jx;
+                J[1 * P + c] = eta * jy;
+                J[2 * P + c] = eta * jz;
+                Q[0 * P + c] = eta * (jz * By[c] - jy * Bz[c]);
+                Q[1 * P + c] = eta * (jx * Bz[c] - jz * Bx[c]);
+                Q[2 * P + c] = eta * (jy * Bx[c] - jx * By[c]);
+            }
+    for (int z = 0; z < G.n[2]; z++)
+        for (int y = 0; y < G.n[1]; y++)
+            for (int x = 0; x < G.n[0]; x++) {
+                long c = at(&G, x, y, z), ic = interior_index(&G, x, y, z);
+                const double *Jx = J, *Jy = J + P, *Jz = J + 2 * P;
+                double rx, ry, rz, re;
+                if (nd == 3) {
+                    rx = cdiff(Jy, c, G.s[2], h[2]) - cdiff(Jz, c, G.s[1], h[1]);
+                    ry = cdiff(Jz, c, G.s[0], h[0]) - cdiff(Jx, c, G.s[2], h[2]);
+                } else {
+                    rx = -cdiff(Jz, c, G.s[1], h[1]);
+                    ry = cdiff(Jz, c, G.s[0], h[0]);
+                }
+                rz = cdiff(Jx, c, G.s[1], h[1]) - cdiff(Jy, c, G.s[0], h[0]);
+                re = cdiff(Q, c, G.s[0], h[0]) + cdiff(Q + P, c, G.s[1], h[1]);
+                if (nd == 3)
+                    re = re + cdiff(Q + 2 * P, c, G.s[2], h[2]);
+                out[BX * G.I + ic] = rx;
+                out[BY * G.I + ic] = ry;
+                out[BZ * G.I + ic] = rz;
+                out[EN * G.I + ic] = re;
+            }
+    free(J);
+    free(Q);
+}
+
+void orc_step_tile(const orc_params *p, const double dx[3], const double *u,
+                   const int n_in[3], const orc_dtrec *dt, double *unew,
+                   double *ff, long *cnt)
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int nv = orc_nvar(p), nd = G.nd;
+    long P = G.P;
+    long dummy[4] = {0, 0, 0, 0};
+    if (!cnt)
+        cnt = dummy;
+    double dtdx[3] = {0, 0, 0}, hdt[3] = {0, 0, 0};
+    for (int d = 0; d < nd; d++) {
+        dtdx[d] = dt->dt / dx[d];
+        hdt[d] = 0.5 * dtdx[d];
+    }
+    double *fh[3] = {NULL, NULL, NULL};
+    for (int d = 0; d < nd; d++)
+        fh[d] = calloc((size_t)nv * P, sizeof(double));
+
+    if (p->scheme == ORC_LF) {
+        double *ut = calloc((size_t)nv * P, sizeof(double));
+        double *sl = calloc((size_t)nd * nv * P, sizeof(double));
+        lf_predict(p, &G, u, hdt, dt->ch, ut, sl, cnt);
+        for (int d = 0; d < nd; d++)
+            lf_faces(p, &G, ut, sl, d, dt->ch, fh[d], cnt);
+        free(ut);
+        free(sl);
+    } else {
+        mmc_fluxes(p, &G, u, dtdx, dt, fh);
+    }
+
+    double *src = NULL, *res = NULL;
+    if (p->physics == ORC_MHD && p->eglm_sources) {
+        src = malloc(sizeof(double) * nv * G.I);
+        orc_eglm_source(p, dx, u, n_in, src);
+    }
+    if (p->physics == ORC_MHD && p->eta > 0.0) {
+        res = malloc(sizeof(double) * nv * G.I);
+        orc_resistive(p, dx, u, n_in, res);
+    }
+
+    /* conservative update (Equ:basic), all directions together */
+    for (int z = 0; z < G.n[2]; z++)
+        for (int y = 0; y < G.n[1]; y++)
+            for (int x = 0; x < G.n[0]; x++) {
+                long c = at(&G, x, y, z), ic = interior_index(&G, x, y, z);
+                double v[NVMAX];
+                for (int k = 0; k < nv; k++) {
+                    double acc = 0.0;
+                    for (int d = 0; d < nd; d++)
+                        acc += dtdx[d] * (fh[d][k * P + c] - fh[d][k * P + c - G.s[d]]);
+                    v[k] = u[k * P + c] - acc;
+                }
+                if (p->physics == ORC_MHD) {
+                    if (src) {
+                        for (int j = 0; j < 3; j++)
+                            v[MX + j] = v[MX + j] + dt->dt * src[(MX + j) * G.I + ic];
+                        v[EN] = v[EN] + dt->dt * src[EN * G.I + ic];
+                    }
+                    if (res) {
+                        for (int j = 0; j < 3; j++)
+                            v[BX + j] = v[BX + j] + dt->dt * res[(BX + j) * G.I + ic];
+                        v[EN] = v[EN] + dt->dt * res[EN * G.I + ic];
+                    }
+                    /* MHD-5 damping term integrated exactly over dt */
+                    v[PSI] = v[PSI] * dt->damp;
+                }
+                for (int k = 0; k < nv; k++)
+                    unew[k * G.I + ic] = v[k];
+            }
+
+    /* fluxes of the block faces, for refluxing */
+    if (ff) {
+        long off = 0;
+        for (int d = 0; d < nd; d++) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            long T = (long)G.n[t1] * G.n[t2];
+            for (int side = 0; side < 2; side++) {
+                int cd = side ? G.n[d] - 1 : -1;
+                for (int k = 0; k < nv; k++)
+                    for (int b = 0; b < G.n[t2]; b++)
+                        for (int a = 0; a < G.n[t1]; a++) {
+                            int xyz[3];
+                            xyz[d] = cd;
+                            xyz[t1] = a;
+                            xyz[t2] = b;
+                            ff[off + k * T + (long)b * G.n[t1] + a] =
+                                fh[d][k * P + at(&G, xyz[0], xyz[1], xyz[2])];
+                        }
+                off += (long)nv * T;
+            }
+        }
+    }
+    free(src);
+    free(res);
+    for (int d = 0; d < nd; d++)
+        free(fh[d]);
+}
+
+double orc_tile_maxspeed(const orc_params *p, const double *u, const int n_in[3])
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int nv = orc_nvar(p);
+    double m = 0.0;
+    for (int z = 0; z < G.n[2]; z++)
+        for (int y = 0; y < G.n[1]; y++)
+            for (int x = 0; x < G.n[0]; x++) {
+                double uc[NVMAX];
+                load(u, G.P, nv, at(&G, x, y, z), uc);
+                for (int d = 0; d < G.nd; d++) {
+                    double s = orc_speed(p, uc, d);
+                    if (s > m)
+                        m = s;
+                }
+            }
+    return m;
+}
+
+/* dt = c_cfl min(dx)/(n_dim alpha_g) (Sec. 3.5); resistive limit by analogy
+ * with the conduction step; c_h and the psi factor per GLM mode (Sec. 2). */
+void orc_make_dtrec(const orc_params *p, double alpha, double dxmin, orc_dtrec *o)
+{
+    int nd = p->ndim;
+    double dt = p->cfl * dxmin / (nd * alpha);
+    if (p->physics == ORC_MHD && p->eta > 0.0) {
+        double dr = p->cfl * dxmin * dxmin / (nd * p->eta);
+        if (dr < dt)
+            dt = dr;
+    }
+    o->dt = dt;
+    o->alpha = alpha;
+    if (p->glm_mode == ORC_GLM_PAPER) {
+        o->ch = p->cfl * dxmin / dt;
+        o->damp = p->cd;
+    } else {
+        o->ch = alpha;
+        o->damp = exp(-dt * o->ch / p->cr);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* monolithic uniform grid                                             */
+/* ------------------------------------------------------------------ */
+static int map_index(int G, int N, int bclo, int bchi)
+{
+    if (G < 0) {
+        if (bclo == ORC_BC_PERIODIC)
+            return ((G % N) + N) % N;
+        return 0;
+    }
+    if (G >= N) {
+        if (bchi == ORC_BC_PERIODIC)
+            return G % N;
+        return N - 1;
+    }
+    return G;
+}
+
+void orc_grid_fill(const orc_params *p, double *u, const int n_in[3], const int bc[3][2])
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int nv = orc_nvar(p);
+    for (int z = -G.g[2]; z < G.n[2] + G.g[2]; z++)
+        for (int y = -G.g[1]; y < G.n[1] + G.g[1]; y++)
+            for (int x = -G.g[0]; x < G.n[0] + G.g[0]; x++) {
+                int xyz[3] = {x, y, z}, src[3];
+                int inside = 1;
+                for (int d = 0; d < 3; d++) {
+                    if (xyz[d] < 0 || xyz[d] >= G.n[d])
+                        inside = 0;
+                    src[d] = map_index(xyz[d], G.n[d], bc[d][0], bc[d][1]);
+                }
+                if (inside)
+                    continue;
+                long c = at(&G, x, y, z), s = at(&G, src[0], src[1], src[2]);
+                for (int k = 0; k < nv; k++)
+                    u[k * G.P + c] = u[k * G.P + s];
+            }
+}
+
+void orc_grid_run(const orc_params *p, const double dx[3], double *u, const int n_in[3],
+                  const int bc[3][2], int nsteps, double *dt_trace, long *cnt)
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int nv = orc_nvar(p);
+    double *unew = malloc(sizeof(double) * nv * G.I);
+    double dxmin = dx[0];
+    for (int d = 1; d < G.nd; d++)
+        if (dx[d] < dxmin)
+            dxmin = dx[d];
+    for (int it = 0; it < nsteps; it++) {
+        orc_grid_fill(p, u, n_in, bc);
+        orc_dtrec r;
+        orc_make_dtrec(p, orc_tile_maxspeed(p, u, n_in), dxmin, &r);
+        if (dt_trace)
+            dt_trace[it] = r.dt;
+        orc_step_tile(p, dx, u, n_in, &r, unew, NULL, cnt);
+        for (int z = 0; z < G.n[2]; z++)
+            for (int y = 0; y < G.n[1]; y++)
+                for (int x = 0; x < G.n[0]; x++)
+                    for (int k = 0; k < nv; k++)
+                        u[k * G.P + at(&G, x, y, z)] = unew[k * G.I + interior_index(&G, x, y, z)];
+    }
+    orc_grid_fill(p, u, n_in, bc);
+    free(unew);
+}
+
+/* ------------------------------------------------------------------ */
+/* block tree                                                          */
+/* ------------------------------------------------------------------ */
+struct orc_amr {
+    orc_params p;
+    int n, nv, nd, nsims, nb, lmax;
+    orc_sim *sims;
+    orc_key *keys;
+    int *order;   /* block indices sorted by key */
+    int *parent;  /* -1 for base blocks */
+    int *haskids;
+    geo G;
+    long T;       /* cells of one block face */
+    double *U;    /* [nb][nv][P] */
+    double *ff;   /* [nb][2 nd][nv][T] */
+    long cnt[4];
+};
+
+static const orc_key *g_sort_keys;
+
+static int key_cmp(const orc_key *a, const orc_key *b)
+{
+    if (a->sim != b->sim) return a->sim < b->sim ? -1 : 1;
+    if (a->level != b->level) return a->level < b->level ? -1 : 1;
+    if (a->iz != b->iz) return a->iz < b->iz ? -1 : 1;
+    if (a->iy != b->iy) return a->iy < b->iy ? -1 : 1;
+    if (a->ix != b->ix) return a->ix < b->ix ? -1 : 1;
+    return 0;
+}
+
+static int idx_cmp(const void *a, const void *b)
+{
+    return key_cmp(&g_sort_keys[*(const int *)a], &g_sort_keys[*(const int *)b]);
+}
+
+static int lookup(const orc_amr *A, int sim, int level, int ix, int iy, int iz)
+{
+    orc_key k = {sim, level, ix, iy, iz};
+    int lo = 0, hi = A->nb - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        int c = key_cmp(&A->keys[A->order[mid]], &k);
+        if (c == 0)
+            return A->order[mid];
+        if (c < 0)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return -1;
+}
+
+static int cells_at_level(const orc_amr *A, int sim, int d, int level)
+{
+    return A->sims[sim].nbase[d] * A->n << (level - 1);
+}
+
+static void block_dx(const orc_amr *A, int b, double dx[3])
+{
+    const orc_key *k = &A->keys[b];
+    for (int d = 0; d < 3; d++) {
+        if (d < A->nd) {
+            const orc_sim *s = &A->sims[k->sim];
+            dx[d] = (s->hi[d] - s->lo[d]) / cells_at_level(A, k->sim, d, k->level);
+        } else {
+            dx[d] = 1.0;
+        }
+    }
+}
+
+static void key_coords(const orc_key *k, int c[3])
+{
+    c[0] = k->ix;
+    c[1] = k->iy;
+    c[2] = k->iz;
+}
+
+orc_amr *orc_amr_new(const orc_params *p, int n, int nsims, const orc_sim *sims,
+                     int nb, const orc_key *keys)
+{
+    orc_amr *A = calloc(1, sizeof(orc_amr));
+    A->p = *p;
+    A->n = n;
+    A->nv = orc_nvar(p);
+    A->nd = p->ndim;
+    A->nsims = nsims;
+    A->nb = nb;
+    A->sims = malloc(sizeof(orc_sim) * nsims);
+    memcpy(A->sims, sims, sizeof(orc_sim) * nsims);
+    A->keys = malloc(sizeof(orc_key) * nb);
+    memcpy(A->keys, keys, sizeof(orc_key) * nb);
+    A->order = malloc(sizeof(int) * nb);
+    for (int i = 0; i < nb; i++)
+        A->order[i] = i;
+    g_sort_keys = A->keys;
+    qsort(A->order, nb, sizeof(int), idx_cmp);
+    int nn[3] = {n, n, n};
+    A->G = mkgeo(A->nd, nn);
+    A->T = (A->nd == 3) ? (long)n * n : n;
+    A->parent = malloc(sizeof(int) * nb);
+    A->haskids = calloc(nb, sizeof(int));
+    A->lmax = 1;
+    for (int b = 0; b < nb; b++) {
+        const orc_key *k = &A->keys[b];
+        if (k->level > A->lmax)
+            A->lmax = k->level;
+        A->parent[b] = -1;
+        if (k->level > 1) {
+            int pb = lookup(A, k->sim, k->level - 1, k->ix >> 1, k->iy >> 1, k->iz >> 1);
+            A->parent[b] = pb;
+            if (pb >= 0)
+                A->haskids[pb] = 1;
+        }
+    }
+    A->U = calloc((size_t)nb * A->nv * A->G.P, sizeof(double));
+    A->ff = calloc((size_t)nb * 2 * A->nd * A->nv * A->T, sizeof(double));
+    return A;
+}
+
+void orc_amr_free(orc_amr *A)
+{
+    if (!A)
+        return;
+    free(A->sims);
+    free(A->keys);
+    free(A->order);
+    free(A->parent);
+    free(A->haskids);
+    free(A->U);
+    free(A->ff);
+    free(A);
+}
+
+double *orc_amr_state(orc_amr *A) { return A->U; }
+int orc_amr_tile_cells(const orc_amr *A) { return (int)A->G.P; }
+int orc_amr_is_leaf(const orc_amr *A, int b) { return !A->haskids[b]; }
+
+void orc_amr_counters(const orc_amr *A, long out[4])
+{
+    for (int i = 0; i < 4; i++)
+        out[i] = A->cnt[i];
+}
+
+static double *tile(orc_amr *A, int b) { return A->U + (size_t)b * A->nv * A->G.P; }
+
+void orc_amr_prim_to_cons(orc_amr *A)
+{
+    for (int b = 0; b < A->nb; b++)
+        orc_prim_to_cons(&A->p, tile(A, b), A->G.P);
+}
+
+/* conservative minmod-limited linear interpolation from the parent's padded
+ * tile (Sec. 4.3, step 6) at fine padded cell (x,y,z) of block b */
+static void prolong_cell(orc_amr *A, int b, int x, int y, int z, double *out)
+{
+    const orc_key *k = &A->keys[b];
+    int pb = A->parent[b];
+    const double *pu = tile(A, pb);
+    int kc[3], loc[3] = {x, y, z}, ci[3], off[3];
+    key_coords(k, kc);
+    for (int d = 0; d < 3; d++) {
+        if (d < A->nd) {
+            int f = (kc[d] & 1) * A->n + loc[d];  /* fine index relative to the parent origin */
+            int c = (f >= 0) ? f / 2 : -((-f + 1) / 2);
+            ci[d] = c;
+            off[d] = f - 2 * c;
+        } else {
+            ci[d] = 0;
+            off[d] = 0;
+        }
+    }
+    long c = at(&A->G, ci[0], ci[1], ci[2]);
+    for (int kv = 0; kv < A->nv; kv++) {
+        const double *q = pu + (long)kv * A->G.P;
+        double v = q[c];
+        for (int d = 0; d < A->nd; d++) {
+            long s = A->G.s[d];
+            double slope = orc_limiter(ORC_MINMOD, q[c + s] - q[c], q[c] - q[c - s]);
+            double w = off[d] ? 0.25 : -0.25;
+            v = v + slope * w;
+        }
+        out[kv] = v;
+    }
+}
+
+typedef struct { int b, x, y, z; } pcell;
+
+void orc_amr_fill(orc_amr *A)
+{
+    geo *G = &A->G;
+    int nv = A->nv, n = A->n;
+    size_t cap = 1024, np = 0;
+    pcell *pl = malloc(sizeof(pcell) * cap);
+    for (int b = 0; b < A->nb; b++) {
+        const orc_key *k = &A->keys[b];
+        const orc_sim *S = &A->sims[k->sim];
+        int kc[3];
+        key_coords(k, kc);
+        double *u = tile(A, b);
+        for (int z = -G->g[2]; z < G->n[2] + G->g[2]; z++)
+            for (int y = -G->g[1]; y < G->n[1] + G->g[1]; y++)
+                for (int x = -G->g[0]; x < G->n[0] + G->g[0]; x++) {
+                    int loc[3] = {x, y, z};
+                    int inside = 1;
+                    for (int d = 0; d < 3; d++)
+                        if (loc[d] < 0 || loc[d] >= G->n[d])
+                            inside = 0;
+                    if (inside)
+                        continue;
+                    int bc3[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
+                    for (int d = 0; d < A->nd; d++) {
+                        int N = cells_at_level(A, k->sim, d, k->level);
+                        int g = map_index(kc[d] * n + loc[d], N, S->bc[d][0], S->bc[d][1]);
+                        bc3[d] = g / n;
+                        lc[d] = g - bc3[d] * n;
+                    }
+                    int src = lookup(A, k->sim, k->level, bc3[0], bc3[1], bc3[2]);
+                    long c = at(G, x, y, z);
+                    if (src >= 0) {
+                        const double *su = tile(A, src);
+                        long sc = at(G, lc[0], lc[1], lc[2]);
+                        for (int kv = 0; kv < nv; kv++)
+                            u[kv * G->P + c] = su[kv * G->P + sc];
+                    } else {
+                        if (np == cap) {
+                            cap *= 2;
+                            pl = realloc(pl, sizeof(pcell) * cap);
+                        }
+                        pl[np].b = b;
+                        pl[np].x = x;
+                        pl[np].y = y;
+                        pl[np].z = z;
+                        np++;
+                    }
+                }
+    }
+    /* coarse to fine, so a parent's own prolonged ghosts are in place */
+    for (int lv = 2; lv <= A->lmax; lv++)
+        for (size_t i = 0; i < np; i++) {
+            if (A->keys[pl[i].b].level != lv)
+                continue;
+            double v[NVMAX];
+            prolong_cell(A, pl[i].b, pl[i].x, pl[i].y, pl[i].z, v);
+            double *u = tile(A, pl[i].b);
+            long c = at(G, pl[i].x, pl[i].y, pl[i].z);
+            for (int kv = 0; kv < nv; kv++)
+                u[kv * G->P + c] = v[kv];
+        }
+    free(pl);
+}
+
+void orc_amr_prolong_block(orc_amr *A, int b)
+{
+    geo *G = &A->G;
+    double *u = tile(A, b);
+    for (int z = 0; z < G->n[2]; z++)
+        for (int y = 0; y < G->n[1]; y++)
+            for (int x = 0; x < G->n[0]; x++) {
+                double v[NVMAX];
+                prolong_cell(A, b, x, y, z, v);
+                for (int kv = 0; kv < A->nv; kv++)
+                    u[kv * G->P + at(G, x, y, z)] = v[kv];
+            }
+}
+
+/* parent = average of its 2^d children's cells (Sec. 4.2, 4.3 step 1),
+ * summed in pairs so that equal inputs give the same value back */
+void orc_amr_restrict(orc_amr *A)
+{
+    geo *G = &A->G;
+    int n = A->n, nd = A->nd;
+    for (int lv = A->lmax - 1; lv >= 1; lv--)
+        for (int b = 0; b < A->nb; b++) {
+            const orc_key *k = &A->keys[b];
+            if (k->level != lv || !A->haskids[b])
+                continue;
+            double *u = tile(A, b);
+            int kc[3];
+            key_coords(k, kc);
+            for (int z = 0; z < G->n[2]; z++)
+                for (int y = 0; y < G->n[1]; y++)
+                    for (int x = 0; x < G->n[0]; x++) {
+                        int loc[3] = {x, y, z};
+                        double f[8][NVMAX];
+                        int nf = 1 << nd;
+                        for (int o = 0; o < nf; o++) {
+                            int cc[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
+                            for (int d = 0; d < nd; d++) {
+                                int fg = 2 * (kc[d] * n + loc[d]) + ((o >> d) & 1);
+                                cc[d] = fg / n;
+                                lc[d] = fg - cc[d] * n;
+                            }
+                            int cb = lookup(A, k->sim, lv + 1, cc[0], cc[1], cc[2]);
+                            load(tile(A, cb), G->P, A->nv, at(G, lc[0], lc[1], lc[2]), f[o]);
+                        }
+                        long c = at(G, x, y, z);
+                        for (int kv = 0; kv < A->nv; kv++) {
+                            double v;
+                            if (nd == 2)
+                                v = ((f[0][kv] + f[1][kv]) + (f[2][kv] + f[3][kv])) * 0.25;
+                            else
+                                v = (((f[0][kv] + f[1][kv]) + (f[2][kv] + f[3][kv]))
+                                     + ((f[4][kv] + f[5][kv]) + (f[6][kv] + f[7][kv]))) * 0.125;
+                            u[kv * G->P + c] = v;
+                        }
+                    }
+        }
+}
+
+static void sim_dxmin(const orc_amr *A, int sim, double *dxmin)
+{
+    double m = 0.0;
+    int first = 1;
+    for (int b = 0; b < A->nb; b++) {
+        if (A->keys[b].sim != sim || A->haskids[b])
+            continue;
+        double dx[3];
+        block_dx(A, b, dx);
+        for (int d = 0; d < A->nd; d++)
+            if (first || dx[d] < m) {
+                m = dx[d];
+                first = 0;
+            }
+    }
+    *dxmin = m;
+}
+
+void orc_amr_cfl(orc_amr *A, orc_dtrec *out)
+{
+    int nn[3] = {A->n, A->n, A->n};
+    for (int s = 0; s < A->nsims; s++) {
+        double alpha = 0.0, dxmin;
+        for (int b = 0; b < A->nb; b++) {
+            if (A->keys[b].sim != s || A->haskids[b])
+                continue;
+            double m = orc_tile_maxspeed(&A->p, tile(A, b), nn);
+            if (m > alpha)
+                alpha = m;
+        }
+        sim_dxmin(A, s, &dxmin);
+        orc_make_dtrec(&A->p, alpha, dxmin, &out[s]);
+    }
+}
+
+void orc_amr_step(orc_amr *A, const orc_dtrec *dt)
+{
+    geo *G = &A->G;
+    int nn[3] = {A->n, A->n, A->n};
+    double *unew = malloc(sizeof(double) * A->nv * G->I);
+    for (int b = 0; b < A->nb; b++) {
+        if (A->haskids[b])
+            continue;
+        double dx[3];
+        block_dx(A, b, dx);
+        double *u = tile(A, b);
+        double *ff = A->ff + (size_t)b * 2 * A->nd * A->nv * A->T;
+        orc_step_tile(&A->p, dx, u, nn, &dt[A->keys[b].sim], unew, ff, A->cnt);
+        for (int z = 0; z < G->n[2]; z++)
+            for (int y = 0; y < G->n[1]; y++)
+                for (int x = 0; x < G->n[0]; x++)
+                    for (int k = 0; k < A->nv; k++)
+                        u[k * G->P + at(G, x, y, z)] = unew[k * G->I + interior_index(G, x, y, z)];
+    }
+    free(unew);
+}
+
+/* Sec. 4.3 step 2: a coarse leaf next to finer leaves replaces its own face
+ * flux by the area mean of the fine face fluxes (same dt on all levels). */
+void orc_amr_reflux(orc_amr *A, const orc_dtrec *dt)
+{
+    geo *G = &A->G;
+    int n = A->n, nd = A->nd, nv = A->nv;
+    long T = A->T;
+    for (int b = 0; b < A->nb; b++) {
+        if (A->haskids[b])
+            continue;
+        const orc_key *k = &A->keys[b];
+        const orc_sim *S = &A->sims[k->sim];
+        int kc[3];
+        key_coords(k, kc);
+        double dx[3];
+        block_dx(A, b, dx);
+        double *u = tile(A, b);
+        for (int d = 0; d < nd; d++) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            for (int side = 0; side < 2; side++) {
+                int nbk[3] = {kc[0], kc[1], kc[2]};
+                int nblocks = S->nbase[d] << (k->level - 1);
+                nbk[d] += side ? 1 : -1;
+                if (nbk[d] < 0 || nbk[d] >= nblocks) {
+                    if (S->bc[d][side] != ORC_BC_PERIODIC)
+                        continue;
+                    nbk[d] = (nbk[d] + nblocks) % nblocks;
+                }
+                int nbb = lookup(A, k->sim, k->level, nbk[0], nbk[1], nbk[2]);
+                if (nbb < 0 || !A->haskids[nbb])
+                    continue;
+                int fside = 1 - side;
+                double dtdx = dt[k->sim].dt / dx[d];
+                const double *fc = A->ff + ((size_t)b * 2 * nd + 2 * d + side) * nv * T;
+                int na = n, nbt = (nd == 3) ? n : 1;
+                for (int tb = 0; tb < nbt; tb++)
+                    for (int ta = 0; ta < na; ta++) {
+                        /* the 2^(d-1) fine faces covering this coarse face */
+                        double fsum[NVMAX];
+                        double fv[4][NVMAX];
+                        int nfine = (nd == 3) ? 4 : 2;
+                        for (int o = 0; o < nfine; o++) {
+                            int fk[3];
+                            int lft[3];
+                            fk[d] = 2 * nbk[d] + (side ? 0 : 1);
+                            int ga = 2 * (kc[t1] * n + ta) + (o & 1);
+                            fk[t1] = ga / n;
+                            lft[t1] = ga - fk[t1] * n;
+                            if (nd == 3) {
+                                int gb = 2 * (kc[t2] * n + tb) + ((o >> 1) & 1);
+                                fk[t2] = gb / n;
+                                lft[t2] = gb - fk[t2] * n;
+                            } else {
+                                fk[t2] = 0;
+                                lft[t2] = 0;
+                            }
+                            int fb = lookup(A, k->sim, k->level + 1, fk[0], fk[1], fk[2]);
+                            const double *ffb = A->ff + ((size_t)fb * 2 * nd + 2 * d + fside) * nv * T;
+                            long t = (long)lft[t2] * n + lft[t1];
+                            for (int kv = 0; kv < nv; kv++)
+                                fv[o][kv] = ffb[kv * T + t];
+                        }
+                        for (int kv = 0; kv < nv; kv++) {
+                            if (nd == 3)
+                                fsum[kv] = ((fv[0][kv] + fv[1][kv]) + (fv[2][kv] + fv[3][kv])) * 0.25;
+                            else
+                                fsum[kv] = (fv[0][kv] + fv[1][kv]) * 0.5;
+                        }
+                        int loc[3];
+                        loc[d] = side ? n - 1 : 0;
+                        loc[t1] = ta;
+                        loc[t2] = tb;
+                        long c = at(G, loc[0], loc[1], loc[2]);
+                        long t = (long)tb * n + ta;
+                        for (int kv = 0; kv < nv; kv++) {
+                            double delta = dtdx * (fc[kv * T + t] - fsum[kv]);
+                            if (side)
+                                u[kv * G->P + c] = u[kv * G->P + c] + delta;
+                            else
+                                u[kv * G->P + c] = u[kv * G->P + c] - delta;
+                        }
+                    }
+            }
+        }
+    }
+}
+
+void orc_amr_totals(const orc_amr *A, double *out)
+{
+    const geo *G = &A->G;
+    memset(out, 0, sizeof(double) * A->nsims * A->nv);
+    for (int b = 0; b < A->nb; b++) {
+        if (A->haskids[b])
+            continue;
+        double dx[3];
+        block_dx(A, b, dx);
+        double vol = dx[0] * dx[1] * (A->nd == 3 ? dx[2] : 1.0);
+        const double *u = A->U + (size_t)b * A->nv * G->P;
+        double *o = out + (size_t)A->keys[b].sim * A->nv;
+        for (int kv = 0; kv < A->nv; kv++)
+            for (int z = 0; z < G->n[2]; z++)
+                for (int y = 0; y < G->n[1]; y++)
+                    for (int x = 0; x < G->n[0]; x++)
+                        o[kv] += u[kv * G->P + at(G, x, y, z)] * vol;
+    }
+}
+
+/* one cycle per step: dt, update of all leaves, reflux, restriction, then
+ * ghost exchange and prolongation (the main loop of Fig. 1 with the boundary
+ * work moved after the update). */
+void orc_amr_run(orc_amr *A, int nsteps, orc_dtrec *trace)
+{
+    orc_dtrec *r = malloc(sizeof(orc_dtrec) * A->nsims);
+    for (int it = 0; it < nsteps; it++) {
+        orc_amr_cfl(A, r);
+        if (trace)
+            memcpy(trace + (size_t)it * A->nsims, r, sizeof(orc_dtrec) * A->nsims);
+        orc_amr_step(A, r);
+        orc_amr_reflux(A, r);
+        orc_amr_restrict(A);
+        orc_amr_fill(A);
+    }
+    free(r);
+}
+
+/* ------------------------------------------------------------------ */
+/* regrid error estimator (Sec. 4.5)                                   */
+/* ------------------------------------------------------------------ */
+static double est_value(const double *u, long P, long c, int mode, int kv)
+{
+    if (mode == 1) {
+        double bx = u[BX * P + c], by = u[BY * P + c], bz = u[BZ * P + c];
+        return sqrt(bx * bx + by * by + bz * bz);
+    }
+    return u[kv * P + c];
+}
+
+double orc_estimate(const orc_params *p, const double *u, const int n_in[3], int mode,
+                    int kv, double eps, double filt, double bias, double ratio,
+                    double xi, int level)
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int lo[3], hi[3];
+    e_range(&G, lo, hi);
+    double scale = pow(ratio, xi * (level - 1));
+    double best = 0.0;
+    for (int z = lo[2]; z < hi[2]; z++)
+        for (int y = lo[1]; y < hi[1]; y++)
+            for (int x = lo[0]; x < hi[0]; x++) {
+                long c = at(&G, x, y, z);
+                double v = est_value(u, G.P, c, mode, kv);
+                double s1 = 0.0, s2 = 0.0;
+                for (int d = 0; d < G.nd; d++) {
+                    double vp = est_value(u, G.P, c + G.s[d], mode, kv);
+                    double vm = est_value(u, G.P, c - G.s[d], mode, kv);
+                    s1 += (vp - vm) * (vp - vm);
+                    s2 += (vp - 2.0 * v + vm) * (vp - 2.0 * v + vm);
+                }
+                double d1 = 0.5 * sqrt(3.0) * sqrt(s1);
+                double d2 = sqrt(s2);
+                double av = fabs(v) + eps;
+                double e = (bias * d1 / av + (1.0 - bias) * d2 / (d1 + filt * av)) * scale;
+                if (e > best)
+                    best = e;
+            }
+    return best;
+}
