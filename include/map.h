@@ -1,0 +1,205 @@
+/*
+ * map.h -- C ABI of the MI355X (gfx950) implementation of the MAP block
+ * update: the EGLM-MHD two-step scheme over a list of equal-sized AMR blocks
+ * (Jiang, Fang & Chen, "MAP: an MHD code with AMR and parallelization").
+ *
+ * Every entry point is extern "C", takes plain pointers and sizes, returns a
+ * map_status (0 = MAP_OK, negative = error) and never throws or aborts; the
+ * text of the last error of the calling thread is map_last_error().  The
+ * library never allocates or frees device memory: the caller owns the state
+ * and a workspace (sizes from map_query) and passes HIP streams as void*.
+ * Work is enqueued asynchronously on the given stream; only map_query,
+ * map_status_flags and map_autotune synchronise.  A context is not thread
+ * safe.  All device pointers must be 256-byte aligned.
+ *
+ * State layout (`U`): [slot][var][z][y][x], FP64 or FP32 (per
+ * map_params.precision), with 16 cells per block edge and 2 ghost layers in
+ * every active dimension (a padded tile of 20^d cells; 2-D tiles have one z
+ * plane).  Variables: rho, m_x, m_y, m_z, B_x, B_y, B_z, e, psi (Sec. 2,
+ * eqs. MHD-1..MHD-5; 2-D runs carry m_z and B_z).  Slots are the blocks in
+ * Morton order (parents before their children, Sec. 4.1); map_query returns
+ * the slot of every input key.
+ */
+#ifndef MAP_H
+#define MAP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct map_ctx map_ctx;  /* opaque, host memory owned by the library */
+
+typedef int map_status;
+enum {
+    MAP_OK = 0,
+    MAP_EINVAL = -1,        /* bad argument (null pointer, unknown enum, bad size) */
+    MAP_ETREE = -2,         /* block list: duplicate, orphan, incomplete base or
+                               sibling set, or 2:1 balance violated */
+    MAP_ENOMEM = -3,        /* workspace smaller than map_query's workspace_bytes */
+    MAP_EHIP = -4,          /* a HIP runtime call failed */
+    MAP_ENONFINITE = -5,    /* reported by map_status_flags: non-finite state */
+    MAP_ENEGPRESSURE = -6,  /* reported by map_status_flags: rho or p <= 0 */
+    MAP_ESTATE = -7         /* call order: workspace not bound */
+};
+
+enum { MAP_FP64 = 0, MAP_FP32_MIXED = 1 };
+enum { MAP_LF = 0, MAP_MMC = 1 };
+enum { MAP_MINMOD = 0, MAP_VANLEER = 1, MAP_PAPER_PHI = 2 };
+enum { MAP_GLM_PAPER = 0, MAP_GLM_FASTSPEED = 1 };
+enum { MAP_BC_PERIODIC = 0, MAP_BC_OUTFLOW = 1 };
+enum { MAP_LAUNCH_BATCHED = 0, MAP_LAUNCH_PER_BLOCK = 1 };
+
+/* Scheme parameters (Sec. 2 and 3).
+ *   precision     MAP_FP64: state and arithmetic in FP64.  MAP_FP32_MIXED:
+ *                 FP32 state and flux arithmetic; pressure recovered in FP64
+ *                 inside every flux/speed evaluation; CFL speeds, dt and the
+ *                 totals in FP64.
+ *   scheme        MAP_LF (TVD-LF: MUSCL-Hancock predictor, Rusanov flux,
+ *                 Sec. 3.2) or MAP_MMC (modified MacCormack, Sec. 3.1).
+ *   limiter       LF: slope limiter; MMC: flux limiter (ratio-free form).
+ *   glm_mode      MAP_GLM_PAPER: c_h = cfl dx_min/dt, psi factor glm_cd per
+ *                 step; MAP_GLM_FASTSPEED: c_h = alpha_g, factor
+ *                 exp(-dt c_h/glm_cr).
+ *   eglm_sources  1: EGLM sources -(div B)B and -B.grad(psi); 0: plain GLM.
+ *   eta           uniform resistivity (0 = off), Sec. 3.5. */
+typedef struct {
+    int ndim, precision, scheme, limiter, glm_mode, eglm_sources;
+    double gamma, cfl, glm_cd, glm_cr, eta;
+} map_params;
+
+/* One simulation: domain box, base-level blocks per dimension, boundary kind
+ * per dimension and side.  Several simulations may share one context. */
+typedef struct {
+    double lo[3], hi[3];
+    int nbase[3];
+    int bc[3][2];
+} map_sim_desc;
+
+/* A block: simulation index, level (base = 1, as in Table 1 of the paper)
+ * and block coordinates at that level. */
+typedef struct {
+    int sim, level, ix, iy, iz;
+} map_block_key;
+
+/* Per-simulation time-step record: dt, GLM speed c_h, psi damping factor
+ * and the global maximum speed alpha_g (Sec. 2 and Sec. 3.7). */
+typedef struct {
+    double dt, ch, damp, alpha;
+} map_dt;
+
+typedef struct {
+    size_t state_bytes;      /* bytes of U */
+    size_t workspace_bytes;  /* bytes of the workspace to bind */
+    int nblocks, nleaves, nsims, max_level, tile_cells, nvar;
+    int n_prolong_items, n_reflux_blocks, n_face_buffers;
+} map_sizes;
+
+/* Validate the block tree and build the neighbour, ghost-descriptor,
+ * restriction and reflux tables ("neighbour statistics", Sec. 4.2) on the
+ * host.  keys lists every block, leaves and parents; every non-base block's
+ * parent and all its siblings must be present, the base level complete, and
+ * the tree 2:1 balanced across faces, edges and corners (with periodic
+ * wrap).  No device work.  On success *ctx owns host memory until
+ * map_destroy.  Errors: MAP_EINVAL, MAP_ETREE. */
+map_status map_init_blocks(map_ctx **ctx, const map_params *params, int nsims,
+                           const map_sim_desc *sims, int nblocks,
+                           const map_block_key *keys);
+
+/* Sizes and the Morton slot of each input key (slot_of_key[nblocks], may be
+ * NULL).  Host only. */
+map_status map_query(const map_ctx *ctx, map_sizes *sizes, int32_t *slot_of_key);
+
+/* Ghost source of every (input key, direction) -- the paper's neighbour
+ * pointers (Table 1) resolved after periodic wrap or outflow clamping:
+ * the input index of the same-level block whose interior cells fill that
+ * direction's ghosts, -1 where the ghosts are prolongated from the parent
+ * (the same-level block does not exist), -2 for direction 0 and for the
+ * unused dz != 0 directions in 2-D.  neigh[nblocks][27], direction index
+ * (dz+1)*9 + (dy+1)*3 + (dx+1).  Host only. */
+map_status map_neighbors(const map_ctx *ctx, int32_t *neigh);
+
+/* Bind a caller-owned device workspace of at least workspace_bytes and
+ * upload the tables on `stream` (asynchronous).  The workspace must outlive
+ * every later call.  Errors: MAP_EINVAL, MAP_ENOMEM, MAP_EHIP. */
+map_status map_bind_workspace(map_ctx *ctx, void *workspace_dev, size_t bytes, void *stream);
+
+/* Convert every cell of U in place from primitive (rho, v, B, p, psi) to
+ * conserved variables, e = p/(gamma-1) + rho v^2/2 + B^2/2 (Sec. 2). */
+map_status map_prim_to_cons(map_ctx *ctx, void *U, void *stream);
+
+/* Ghost layers of every block (Sec. 4.3, steps 3-7): same-level copies
+ * including edge and corner neighbours, periodic wrap or zero-gradient
+ * outflow at the domain edge, then minmod-limited conservative prolongation
+ * from the parent's padded tile for ghosts whose same-level block does not
+ * exist, level by level from coarse to fine. */
+map_status map_fill_ghosts(map_ctx *ctx, void *U, void *stream);
+
+/* Parent interiors = mean of their 2^d children (Sec. 4.3 step 1), from the
+ * finest level down. */
+map_status map_restrict(map_ctx *ctx, void *U, void *stream);
+
+/* Whole-block prolongation (regrid initialisation): the interiors of the
+ * blocks in slots_dev[n] (device int32 slots, level >= 2) from their
+ * parents' padded tiles with the interpolation of Sec. 4.3 step 6. */
+map_status map_prolong(map_ctx *ctx, void *U, const int32_t *slots_dev, int n, void *stream);
+
+/* alpha_g = max over leaf interior cells of |v_d| + c_f,d per simulation,
+ * then dt = cfl dx_min/(n_dim alpha_g) (Sec. 3.7; capped by the resistive
+ * limit cfl dx_min^2/(n_dim eta)), c_h and the psi factor; writes
+ * dt_dev[nsims] (device memory).  Speeds are computed in FP64. */
+map_status map_cfl_dt(map_ctx *ctx, const void *U, map_dt *dt_dev, void *stream);
+
+/* One two-step update of every leaf of every simulation (Sec. 3.1 or 3.2,
+ * all directions together, Sec. 3.7) with EGLM sources, resistivity and
+ * psi damping, reading padded tiles of U_in and writing interiors of U_out
+ * (U_out may equal U_in).  Also stores the fluxes of faces shared with
+ * leaves of another level, for map_reflux. */
+map_status map_step(map_ctx *ctx, const void *U_in, void *U_out, const map_dt *dt_dev,
+                    void *stream);
+
+/* Coarse leaves next to finer leaves replace their face flux by the area
+ * mean of the fine fluxes (Sec. 4.3 step 2).  Run after map_step. */
+map_status map_reflux(map_ctx *ctx, void *U, const map_dt *dt_dev, void *stream);
+
+/* FP64 volume-weighted totals of the conserved variables over the leaves of
+ * each simulation, totals_dev[nsims][9] (device), fixed reduction order. */
+map_status map_totals(map_ctx *ctx, const void *U, double *totals_dev, void *stream);
+
+/* Counters latched by the kernels since the last call, then cleared:
+ * [0] LF cells whose slopes fell back to zero, [1] face states replaced by
+ * the cell average, [2] non-positive rho or p seen by the CFL pass,
+ * [3] non-finite values seen by the CFL pass.  Synchronises `stream`.
+ * Returns MAP_ENONFINITE or MAP_ENEGPRESSURE if [3] or [2] is non-zero. */
+map_status map_status_flags(map_ctx *ctx, uint64_t counters[4], void *stream);
+
+/* nsteps full cycles: cfl_dt, step, reflux, restrict, fill_ghosts, with
+ * dt kept on the device (the record of the last step is copied to dt_dev
+ * if it is not NULL).  Eager launches on `stream`. */
+map_status map_advance(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
+
+/* Same cycle as map_advance, captured once per U into a HIP graph and
+ * replayed nsteps times on `stream`. */
+map_status map_graph_run(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
+
+/* MAP_LAUNCH_BATCHED: one launch per stage over the joint work list of all
+ * levels and simulations (persistent workgroups); MAP_LAUNCH_PER_BLOCK: one
+ * launch per block (the plain baseline).  grid_step / grid_fill: number of
+ * workgroups of the batched step / fill launches (0 = one per work item). */
+map_status map_set_launch(map_ctx *ctx, int mode, int grid_step, int grid_fill);
+
+/* Time the batched step and fill launches over a set of grid sizes on U with
+ * HIP events and keep the fastest (project autotuner); writes the chosen
+ * sizes to chosen[2] if not NULL.  Synchronises `stream`; U is overwritten
+ * with one extra step per trial. */
+map_status map_autotune(map_ctx *ctx, void *U, int *chosen, void *stream);
+
+const char *map_last_error(void);
+void map_destroy(map_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -610,8 +610,8 @@ double orc_tile_maxspeed(const orc_params *p, const double *u, const int n_in[3]
     return m;
 }
 
-/* dt = c_cfl min(dx)/(n_dim alpha_g) (Sec. 3.5); resistive limit by analogy
- * with the conduction step; c_h and the psi factor per GLM mode (Sec. 2). */
+/* dt = c_cfl min(dx)/(n_dim alpha_g) (Sec. 3.7); resistive limit by analogy
+ * with the conduction step of Sec. 3.4; c_h and the psi factor per GLM mode (Sec. 2). */
 void orc_make_dtrec(const orc_params *p, double alpha, double dxmin, orc_dtrec *o)
 {
     int nd = p->ndim;

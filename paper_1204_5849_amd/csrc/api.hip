@@ -1,0 +1,610 @@
+// api.hip -- the extern "C" entry points of libmap.so: argument checks, the
+// device binding of the planned tables, stage launches (batched persistent or
+// one launch per block), the step cycle, its HIP-graph capture and the launch
+// autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace mapk;
+
+namespace {
+
+thread_local std::string g_err;
+
+map_status fail(map_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(MAP_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+template <typename X>
+X *dptr(map_ctx *c, size_t off)
+{
+    return reinterpret_cast<X *>(c->wsp + off);
+}
+
+map_status need_bound(map_ctx *c)
+{
+    if (!c)
+        return fail(MAP_EINVAL, "null context");
+    if (!c->bound)
+        return fail(MAP_ESTATE, "workspace not bound (call map_bind_workspace first)");
+    return MAP_OK;
+}
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool fp64(const map_ctx *c) { return c->p.precision == MAP_FP64; }
+
+map_status run_fill(map_ctx *c, void *U, hipStream_t s)
+{
+    FillArgs a{};
+    a.U = U;
+    a.desc = dptr<Desc>(c, c->ws.desc);
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.parent = dptr<int32_t>(c, c->ws.parent);
+    const int bpw = fill_blocks_per_group(c->nd);
+    if (c->launch_mode == MAP_LAUNCH_PER_BLOCK) {
+        for (int sl = 0; sl < c->nslots; sl++) {
+            a.slot_base = sl;
+            a.slot_end = sl + 1;
+            a.nitems = 1;
+            HIPCHK(launch_fill_copy(c->nd, fp64(c), a, 1, s));
+        }
+    } else {
+        a.slot_base = 0;
+        a.slot_end = c->nslots;
+        a.nitems = (c->nslots + bpw - 1) / bpw;
+        HIPCHK(launch_fill_copy(c->nd, fp64(c), a, c->grid_fill, s));
+    }
+    for (int l = 2; l <= c->lmax; l++) {
+        int lo = c->prolong_off[l], hi = c->prolong_off[l + 1];
+        if (hi <= lo)
+            continue;
+        a.list = dptr<int32_t>(c, c->ws.prolong_list) + lo;
+        a.nitems = hi - lo;
+        HIPCHK(launch_prolong_ghosts(c->nd, fp64(c), a, s));
+    }
+    return MAP_OK;
+}
+
+map_status run_restrict(map_ctx *c, void *U, hipStream_t s)
+{
+    RestrictArgs a{};
+    a.U = U;
+    a.children = dptr<int32_t>(c, c->ws.children);
+    for (int l = c->lmax - 1; l >= 1; l--) {
+        int lo = c->restrict_off[l], hi = c->restrict_off[l + 1];
+        if (hi <= lo)
+            continue;
+        a.list = dptr<int32_t>(c, c->ws.restrict_list) + lo;
+        a.nitems = hi - lo;
+        HIPCHK(launch_restrict(c->nd, fp64(c), a, s));
+    }
+    return MAP_OK;
+}
+
+map_status run_cfl(map_ctx *c, const void *U, map_dt *dt_out, hipStream_t s)
+{
+    CflArgs a{};
+    a.U = U;
+    a.cnt = dptr<unsigned long long>(c, c->ws.counters);
+    a.gamma = c->p.gamma;
+    if (c->launch_mode == MAP_LAUNCH_PER_BLOCK) {
+        for (int i = 0; i < c->nleaves; i++) {
+            a.leaves = dptr<int32_t>(c, c->ws.leaves) + i;
+            a.nleaves = 1;
+            a.part = dptr<double>(c, c->ws.cfl_part) + i;
+            HIPCHK(launch_cfl(c->nd, fp64(c), a, s));
+        }
+    } else {
+        a.leaves = dptr<int32_t>(c, c->ws.leaves);
+        a.nleaves = c->nleaves;
+        a.part = dptr<double>(c, c->ws.cfl_part);
+        HIPCHK(launch_cfl(c->nd, fp64(c), a, s));
+    }
+    DtArgs d{};
+    d.part = dptr<double>(c, c->ws.cfl_part);
+    d.sims = dptr<SimRec>(c, c->ws.sims);
+    d.dt_int = dptr<map_dt>(c, c->ws.dt);
+    d.dt_out = dt_out;
+    d.nsims = (int)c->sims.size();
+    d.ndim = c->nd;
+    d.glm_mode = c->p.glm_mode;
+    d.cfl = c->p.cfl;
+    d.cd = c->p.glm_cd;
+    d.cr = c->p.glm_cr;
+    d.eta = c->p.eta;
+    HIPCHK(launch_dt(d, s));
+    return MAP_OK;
+}
+
+map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, hipStream_t s)
+{
+    StepArgs a{};
+    a.Uin = Uin;
+    a.Uout = Uout;
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.dt = dt;
+    a.lvl_dx = dptr<double>(c, c->ws.lvl_dx);
+    a.fbidx = dptr<int32_t>(c, c->ws.fbidx);
+    a.fbuf = c->wsp + c->ws.fbuf;
+    a.cnt = dptr<unsigned long long>(c, c->ws.counters);
+    a.gamma = c->p.gamma;
+    a.eta = c->p.eta;
+    a.eglm = c->p.eglm_sources;
+    a.limiter = c->p.limiter;
+    const bool resist = c->p.eta > 0.0;
+    auto launch = [&](const StepArgs &x, int grid) -> hipError_t {
+        if (c->p.scheme == MAP_MMC)
+            return launch_step_mmc(c->nd, fp64(c), x, 0.0, grid, s);
+        return launch_step_lf(c->nd, fp64(c), resist, x, grid, s);
+    };
+    const int bpw = step_blocks_per_group(c->nd, c->p.scheme);
+    if (c->launch_mode == MAP_LAUNCH_PER_BLOCK) {
+        for (int i = 0; i < c->nleaves; i++) {
+            a.leaves = dptr<int32_t>(c, c->ws.leaves) + i;
+            a.nleaves = 1;
+            a.nitems = 1;
+            HIPCHK(launch(a, 1));
+        }
+    } else {
+        a.leaves = dptr<int32_t>(c, c->ws.leaves);
+        a.nleaves = c->nleaves;
+        a.nitems = (c->nleaves + bpw - 1) / bpw;
+        HIPCHK(launch(a, c->grid_step));
+    }
+    return MAP_OK;
+}
+
+map_status run_reflux(map_ctx *c, void *U, const map_dt *dt, hipStream_t s)
+{
+    if (c->reflux_slots.empty())
+        return MAP_OK;
+    RefluxArgs a{};
+    a.U = U;
+    a.slots = dptr<int32_t>(c, c->ws.reflux_slots);
+    a.start = dptr<int32_t>(c, c->ws.reflux_start);
+    a.recs = dptr<RefluxRec>(c, c->ws.reflux_recs);
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.dt = dt;
+    a.lvl_dx = dptr<double>(c, c->ws.lvl_dx);
+    a.fbuf = c->wsp + c->ws.fbuf;
+    a.nitems = (int)c->reflux_slots.size();
+    HIPCHK(launch_reflux(c->nd, fp64(c), a, s));
+    return MAP_OK;
+}
+
+map_status run_cycle(map_ctx *c, void *U, hipStream_t s)
+{
+    map_dt *dt = dptr<map_dt>(c, c->ws.dt);
+    map_status st;
+    if ((st = run_cfl(c, U, nullptr, s)) != MAP_OK)
+        return st;
+    if ((st = run_step(c, U, U, dt, s)) != MAP_OK)
+        return st;
+    if ((st = run_reflux(c, U, dt, s)) != MAP_OK)
+        return st;
+    if ((st = run_restrict(c, U, s)) != MAP_OK)
+        return st;
+    return run_fill(c, U, s);
+}
+
+void drop_graph(map_ctx *c)
+{
+    if (c->graph_exec) {
+        hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(c->graph_exec));
+        c->graph_exec = nullptr;
+    }
+    c->graph_U = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *map_last_error(void) { return g_err.c_str(); }
+
+map_status map_init_blocks(map_ctx **ctx, const map_params *params, int nsims,
+                           const map_sim_desc *sims, int nblocks, const map_block_key *keys)
+{
+    if (!ctx)
+        return fail(MAP_EINVAL, "null ctx pointer");
+    *ctx = nullptr;
+    map_ctx *c = new (std::nothrow) map_ctx();
+    if (!c)
+        return fail(MAP_EINVAL, "out of host memory");
+    std::string err;
+    map_status st;
+    try {
+        st = map_plan_build(c, params, nsims, sims, nblocks, keys, err);
+    } catch (const std::exception &e) {
+        st = MAP_EINVAL;
+        err = std::string("host exception: ") + e.what();
+    }
+    if (st != MAP_OK) {
+        delete c;
+        return fail(st, err);
+    }
+    *ctx = c;
+    return MAP_OK;
+}
+
+map_status map_query(const map_ctx *c, map_sizes *sz, int32_t *slot_of_key)
+{
+    if (!c || !sz)
+        return fail(MAP_EINVAL, "null argument");
+    sz->state_bytes = (size_t)c->nslots * NV * c->tile * c->word;
+    sz->workspace_bytes = c->ws.total;
+    sz->nblocks = c->nslots;
+    sz->nleaves = c->nleaves;
+    sz->nsims = (int)c->sims.size();
+    sz->max_level = c->lmax;
+    sz->tile_cells = c->tile;
+    sz->nvar = NV;
+    sz->n_prolong_items = (int)c->prolong_list.size();
+    sz->n_reflux_blocks = (int)c->reflux_slots.size();
+    sz->n_face_buffers = c->nfb;
+    if (slot_of_key)
+        std::memcpy(slot_of_key, c->slot_of_key.data(), sizeof(int32_t) * c->nslots);
+    return MAP_OK;
+}
+
+/* Ghost source of every (input key, direction): the input index of the
+ * same-level block whose cells are copied, -1 where ghosts are prolongated
+ * from the parent, -2 for the block itself (direction 0) or unused
+ * directions (dz != 0 in 2-D).  neigh[nblocks][27], direction index
+ * (dz+1)*9 + (dy+1)*3 + (dx+1).  Host only. */
+map_status map_neighbors(const map_ctx *c, int32_t *neigh)
+{
+    if (!c || !neigh)
+        return fail(MAP_EINVAL, "null argument");
+    std::vector<int32_t> key_of_slot(c->nslots);
+    for (int i = 0; i < c->nslots; i++)
+        key_of_slot[c->slot_of_key[i]] = i;
+    for (int i = 0; i < c->nslots; i++) {
+        int s = c->slot_of_key[i];
+        for (int d = 0; d < NDIR; d++) {
+            int src = c->desc[(size_t)s * NDIR + d].src;
+            neigh[(size_t)i * NDIR + d] = src >= 0 ? key_of_slot[src] : src;
+        }
+    }
+    return MAP_OK;
+}
+
+map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
+{
+    if (!c || !ws)
+        return fail(MAP_EINVAL, "null argument");
+    if (bytes < c->ws.total)
+        return fail(MAP_ENOMEM, "workspace of " + std::to_string(bytes) + " bytes, need " +
+                                    std::to_string(c->ws.total));
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0)
+        return fail(MAP_EINVAL, "workspace must be 256-byte aligned");
+    drop_graph(c);
+    c->wsp = static_cast<char *>(ws);
+    hipStream_t s = S(stream);
+    auto up = [&](size_t off, const void *src, size_t n) -> hipError_t {
+        if (n == 0)
+            return hipSuccess;
+        return hipMemcpyAsync(c->wsp + off, src, n, hipMemcpyHostToDevice, s);
+    };
+    HIPCHK(up(c->ws.blocks, c->blk.data(), c->blk.size() * sizeof(BlockRec)));
+    HIPCHK(up(c->ws.desc, c->desc.data(), c->desc.size() * sizeof(Desc)));
+    HIPCHK(up(c->ws.parent, c->parent.data(), c->parent.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.children, c->children.data(), c->children.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.fbidx, c->fbidx.data(), c->fbidx.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.leaves, c->leaves.data(), c->leaves.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.restrict_list, c->restrict_list.data(), c->restrict_list.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.prolong_list, c->prolong_list.data(), c->prolong_list.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.reflux_slots, c->reflux_slots.data(), c->reflux_slots.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.reflux_start, c->reflux_start.data(), c->reflux_start.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.reflux_recs, c->reflux_recs.data(), c->reflux_recs.size() * sizeof(RefluxRec)));
+    HIPCHK(up(c->ws.sims, c->simrec.data(), c->simrec.size() * sizeof(SimRec)));
+    HIPCHK(up(c->ws.lvl_dx, c->lvl_dx.data(), c->lvl_dx.size() * sizeof(double)));
+    HIPCHK(launch_clear_u64(dptr<unsigned long long>(c, c->ws.counters), 4, s));
+    // the host vectors above are pageable: finish the copies before returning
+    HIPCHK(hipStreamSynchronize(s));
+    c->bound = true;
+    return MAP_OK;
+}
+
+map_status map_prim_to_cons(map_ctx *c, void *U, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U)
+        return fail(MAP_EINVAL, "null U");
+    HIPCHK(launch_prim_to_cons(fp64(c), U, (size_t)c->nslots, c->tile, c->p.gamma, S(stream)));
+    return MAP_OK;
+}
+
+map_status map_fill_ghosts(map_ctx *c, void *U, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U)
+        return fail(MAP_EINVAL, "null U");
+    return run_fill(c, U, S(stream));
+}
+
+map_status map_restrict(map_ctx *c, void *U, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U)
+        return fail(MAP_EINVAL, "null U");
+    return run_restrict(c, U, S(stream));
+}
+
+map_status map_prolong(map_ctx *c, void *U, const int32_t *slots_dev, int n, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U || (n > 0 && !slots_dev) || n < 0)
+        return fail(MAP_EINVAL, "null U or slot list");
+    FillArgs a{};
+    a.U = U;
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.parent = dptr<int32_t>(c, c->ws.parent);
+    a.list = slots_dev;
+    a.nitems = n;
+    HIPCHK(launch_prolong_blocks(c->nd, fp64(c), a, S(stream)));
+    return MAP_OK;
+}
+
+map_status map_cfl_dt(map_ctx *c, const void *U, map_dt *dt_dev, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U)
+        return fail(MAP_EINVAL, "null U");
+    return run_cfl(c, U, dt_dev, S(stream));
+}
+
+map_status map_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt_dev, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!Uin || !Uout || !dt_dev)
+        return fail(MAP_EINVAL, "null U or dt");
+    return run_step(c, Uin, Uout, dt_dev, S(stream));
+}
+
+map_status map_reflux(map_ctx *c, void *U, const map_dt *dt_dev, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U || !dt_dev)
+        return fail(MAP_EINVAL, "null U or dt");
+    return run_reflux(c, U, dt_dev, S(stream));
+}
+
+map_status map_totals(map_ctx *c, const void *U, double *totals_dev, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U || !totals_dev)
+        return fail(MAP_EINVAL, "null U or output");
+    TotalsArgs a{};
+    a.U = U;
+    a.leaves = dptr<int32_t>(c, c->ws.leaves);
+    a.nleaves = c->nleaves;
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.lvl_dx = dptr<double>(c, c->ws.lvl_dx);
+    a.part = dptr<double>(c, c->ws.tot_part);
+    a.sims = dptr<SimRec>(c, c->ws.sims);
+    a.out = totals_dev;
+    a.nsims = (int)c->sims.size();
+    a.ndim = c->nd;
+    HIPCHK(launch_totals(c->nd, fp64(c), a, S(stream)));
+    return MAP_OK;
+}
+
+map_status map_status_flags(map_ctx *c, uint64_t counters[4], void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!counters)
+        return fail(MAP_EINVAL, "null counters");
+    hipStream_t s = S(stream);
+    unsigned long long h[4];
+    HIPCHK(hipMemcpyAsync(h, c->wsp + c->ws.counters, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(launch_clear_u64(dptr<unsigned long long>(c, c->ws.counters), 4, s));
+    for (int i = 0; i < 4; i++)
+        counters[i] = h[i];
+    if (h[3])
+        return fail(MAP_ENONFINITE, std::to_string(h[3]) + " non-finite cells");
+    if (h[2])
+        return fail(MAP_ENEGPRESSURE, std::to_string(h[2]) + " cells with rho <= 0 or p <= 0");
+    return MAP_OK;
+}
+
+map_status map_advance(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U || nsteps < 0)
+        return fail(MAP_EINVAL, "null U or negative step count");
+    hipStream_t s = S(stream);
+    for (int i = 0; i < nsteps; i++)
+        if ((st = run_cycle(c, U, s)) != MAP_OK)
+            return st;
+    if (dt_dev && nsteps > 0)
+        HIPCHK(hipMemcpyAsync(dt_dev, c->wsp + c->ws.dt, sizeof(map_dt) * c->sims.size(),
+                              hipMemcpyDeviceToDevice, s));
+    return MAP_OK;
+}
+
+map_status map_graph_run(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U || nsteps < 0)
+        return fail(MAP_EINVAL, "null U or negative step count");
+    hipStream_t s = S(stream);
+    if (!c->graph_exec || c->graph_U != U) {
+        drop_graph(c);
+        if (!c->cap_stream) {
+            hipStream_t cs;
+            HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            c->cap_stream = cs;
+        }
+        hipStream_t cs = S(c->cap_stream);
+        HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+        st = run_cycle(c, U, cs);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs, &g);
+        if (st != MAP_OK) {
+            if (g)
+                hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess)
+            return fail(MAP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return fail(MAP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        c->graph_exec = ex;
+        c->graph_U = U;
+    }
+    for (int i = 0; i < nsteps; i++)
+        HIPCHK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(c->graph_exec), s));
+    if (dt_dev && nsteps > 0)
+        HIPCHK(hipMemcpyAsync(dt_dev, c->wsp + c->ws.dt, sizeof(map_dt) * c->sims.size(),
+                              hipMemcpyDeviceToDevice, s));
+    return MAP_OK;
+}
+
+map_status map_set_launch(map_ctx *c, int mode, int grid_step, int grid_fill)
+{
+    if (!c)
+        return fail(MAP_EINVAL, "null context");
+    if (mode != MAP_LAUNCH_BATCHED && mode != MAP_LAUNCH_PER_BLOCK)
+        return fail(MAP_EINVAL, "unknown launch mode");
+    if (grid_step < 0 || grid_fill < 0)
+        return fail(MAP_EINVAL, "negative grid size");
+    drop_graph(c);
+    c->launch_mode = mode;
+    c->grid_step = grid_step;
+    c->grid_fill = grid_fill;
+    return MAP_OK;
+}
+
+map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U)
+        return fail(MAP_EINVAL, "null U");
+    hipStream_t s = S(stream);
+    const int saved_mode = c->launch_mode;
+    c->launch_mode = MAP_LAUNCH_BATCHED;
+    const int bpw = step_blocks_per_group(c->nd, c->p.scheme);
+    const int nstep = (c->nleaves + bpw - 1) / bpw;
+    const int fbpw = fill_blocks_per_group(c->nd);
+    const int nfill = (c->nslots + fbpw - 1) / fbpw;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    map_dt *dt = dptr<map_dt>(c, c->ws.dt);
+    if ((st = run_cfl(c, U, nullptr, s)) != MAP_OK)
+        return st;
+    auto time_it = [&](auto &&fn) -> float {
+        float best = 1e30f;
+        for (int r = 0; r < 3; r++) {
+            hipEventRecord(e0, s);
+            if (fn() != MAP_OK)
+                return 1e30f;
+            hipEventRecord(e1, s);
+            hipEventSynchronize(e1);
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            best = std::min(best, ms);
+        }
+        return best;
+    };
+    // candidate persistent grids: multiples of the 256 compute units, and
+    // one workgroup per work item (0)
+    std::vector<int> cands = {0};
+    for (int m : {1, 2, 4, 8, 16})
+        if (256 * m < nstep)
+            cands.push_back(256 * m);
+    int best_step = 0;
+    float best_t = 1e30f;
+    for (int g : cands) {
+        c->grid_step = g;
+        float t = time_it([&] { return run_step(c, U, U, dt, s); });
+        if (t < best_t) {
+            best_t = t;
+            best_step = g;
+        }
+    }
+    std::vector<int> fc = {0};
+    for (int m : {1, 2, 4, 8, 16})
+        if (256 * m < nfill)
+            fc.push_back(256 * m);
+    int best_fill = 0;
+    best_t = 1e30f;
+    for (int g : fc) {
+        c->grid_fill = g;
+        float t = time_it([&] { return run_fill(c, U, s); });
+        if (t < best_t) {
+            best_t = t;
+            best_fill = g;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    drop_graph(c);
+    c->launch_mode = saved_mode;
+    c->grid_step = best_step;
+    c->grid_fill = best_fill;
+    if (chosen) {
+        chosen[0] = best_step;
+        chosen[1] = best_fill;
+    }
+    return MAP_OK;
+}
+
+void map_destroy(map_ctx *c)
+{
+    if (!c)
+        return;
+    drop_graph(c);
+    if (c->cap_stream)
+        hipStreamDestroy(S(c->cap_stream));
+    delete c;
+}
+
+}  // extern "C"

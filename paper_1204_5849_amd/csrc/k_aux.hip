@@ -1,0 +1,607 @@
+// k_aux.hip -- the data-motion and reduction stages around the block update:
+// ghost copies with periodic / outflow edges, conservative prolongation,
+// restriction, reflux (paper Sec. 4.3), the CFL reduction and time-step record
+// (Sec. 2, Sec. 3.7), FP64 totals and the primitive-to-conserved conversion.
+//
+// These kernels are HBM-bound gathers and scatters: threads walk the ghost
+// frame (or interior) of a block in the padded tile's own linear order so
+// that writes are contiguous rows, and each thread moves all nine variables
+// of its cell.  Contraction of a*b+c into FMA is switched off here so the
+// arithmetic follows the written order exactly (it costs nothing in a
+// memory-bound kernel).
+#include "kernels.hpp"
+#include "physics.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mapk {
+
+template <int NDIM>
+struct FG;
+template <>
+struct FG<2> {
+    static constexpr int P = PD * PD, NGC = PD * PD - NB * NB, BPW = 16, NI = NB * NB;
+};
+template <>
+struct FG<3> {
+    static constexpr int P = PD * PD * PD, NGC = PD * PD * PD - NB * NB * NB, BPW = 1,
+                         NI = NB * NB * NB;
+};
+constexpr int NTA = 256;
+
+template <int NDIM>
+__device__ __forceinline__ int lin(int x, int y, int z)
+{
+    if constexpr (NDIM == 3)
+        return ((z + NG) * PD + (y + NG)) * PD + (x + NG);
+    return (y + NG) * PD + (x + NG);
+}
+
+// g-th ghost cell of a block, enumerated in the padded tile's linear order
+// by regions: the ghost planes/rows below and above, then the side strips
+template <int NDIM>
+__device__ __forceinline__ void ghost_xyz(int g, int &x, int &y, int &z)
+{
+    if constexpr (NDIM == 2) {
+        z = 0;
+        if (g < 4 * PD) {
+            int r = g / PD;
+            x = g - r * PD - NG;
+            y = r < 2 ? r - 2 : r + NB - 2;
+        } else {
+            g -= 4 * PD;
+            int r = g >> 2, c = g & 3;
+            y = r;
+            x = c < 2 ? c - 2 : c + NB - 2;
+        }
+    } else {
+        if (g < 4 * PD * PD) {
+            int pl = g / (PD * PD), r = g - pl * PD * PD;
+            z = pl < 2 ? pl - 2 : pl + NB - 2;
+            y = r / PD - NG;
+            x = r % PD - NG;
+        } else if (g < 4 * PD * PD + NB * 4 * PD) {
+            g -= 4 * PD * PD;
+            z = g / (4 * PD);
+            int r = g - z * 4 * PD, row = r / PD;
+            y = row < 2 ? row - 2 : row + NB - 2;
+            x = r % PD - NG;
+        } else {
+            g -= 4 * PD * PD + NB * 4 * PD;
+            z = g / (NB * 4);
+            int r = g - z * NB * 4;
+            y = r >> 2;
+            int c = r & 3;
+            x = c < 2 ? c - 2 : c + NB - 2;
+        }
+    }
+}
+
+template <int NDIM>
+__device__ __forceinline__ int dir_index(int x, int y, int z)
+{
+    int dx = x < 0 ? -1 : (x >= NB ? 1 : 0);
+    int dy = y < 0 ? -1 : (y >= NB ? 1 : 0);
+    int dz = NDIM == 3 ? (z < 0 ? -1 : (z >= NB ? 1 : 0)) : 0;
+    return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+}
+
+__device__ __forceinline__ int src_index(int g, int o) { return o >= CLAMP ? o - CLAMP : g + o; }
+
+// ---- same-level copies and physical edges (descriptor src >= 0)
+template <int NDIM, typename T>
+__global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
+{
+    constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC, BPW = FG<NDIM>::BPW;
+    T *U = (T *)a.U;
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        for (int g = threadIdx.x; g < BPW * NGC; g += NTA) {
+            const int lb = g / NGC, gi = g - lb * NGC;
+            const int slot = a.slot_base + item * BPW + lb;
+            if (slot >= a.slot_end)
+                break;
+            int x, y, z;
+            ghost_xyz<NDIM>(gi, x, y, z);
+            const Desc ds = a.desc[(size_t)slot * NDIR + dir_index<NDIM>(x, y, z)];
+            if (ds.src < 0)
+                continue;
+            const int sx = src_index(x, ds.o0), sy = src_index(y, ds.o1);
+            const int sz = NDIM == 3 ? src_index(z, ds.o2) : 0;
+            T *dst = U + (size_t)slot * NV * P + lin<NDIM>(x, y, z);
+            const T *src = U + (size_t)ds.src * NV * P + lin<NDIM>(sx, sy, sz);
+            T v[NV];
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                v[k] = src[(size_t)k * P];
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                dst[(size_t)k * P] = v[k];
+        }
+    }
+}
+
+// minmod-limited linear interpolation from the parent's padded tile at fine
+// padded cell (x, y, z) of a child in position cpos (Sec. 4.3, step 6)
+template <int NDIM, typename T>
+__device__ __forceinline__ void prolong_cell(const T *pu, int cpos, int x, int y, int z, T out[NV])
+{
+    constexpr int P = FG<NDIM>::P;
+    const int loc[3] = {x, y, z};
+    int ci[3] = {0, 0, 0};
+    T w[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int d = 0; d < NDIM; d++) {
+        int f = ((cpos >> d) & 1) * NB + loc[d];
+        ci[d] = f >> 1;  // floor(f / 2), also for f < 0
+        w[d] = (f & 1) ? T(0.25) : T(-0.25);
+    }
+    const int c = lin<NDIM>(ci[0], ci[1], ci[2]);
+    const int st[3] = {1, PD, PD * PD};
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        const T *q = pu + (size_t)k * P;
+        T val = q[c];
+        T v = val;
+#pragma unroll
+        for (int d = 0; d < NDIM; d++) {
+            T s = lim_minmod(q[c + st[d]] - val, val - q[c - st[d]]);
+            v = v + s * w[d];
+        }
+        out[k] = v;
+    }
+}
+
+// ---- prolongated ghosts of the blocks of one level (descriptor src == -1)
+template <int NDIM, typename T>
+__global__ void __launch_bounds__(NTA) k_prolong_ghosts(FillArgs a)
+{
+    constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC;
+    T *U = (T *)a.U;
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        const int slot = a.list[item];
+        const int par = a.parent[slot];
+        const int cpos = a.blk[slot].cpos;
+        const T *pu = U + (size_t)par * NV * P;
+        T *ub = U + (size_t)slot * NV * P;
+        for (int g = threadIdx.x; g < NGC; g += NTA) {
+            int x, y, z;
+            ghost_xyz<NDIM>(g, x, y, z);
+            const Desc ds = a.desc[(size_t)slot * NDIR + dir_index<NDIM>(x, y, z)];
+            if (ds.src != -1)
+                continue;
+            T v[NV];
+            prolong_cell<NDIM, T>(pu, cpos, x, y, z, v);
+            const int c = lin<NDIM>(x, y, z);
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                ub[(size_t)k * P + c] = v[k];
+        }
+    }
+}
+
+// ---- whole-block prolongation (regrid initialisation)
+template <int NDIM, typename T>
+__global__ void __launch_bounds__(NTA) k_prolong_blocks(FillArgs a)
+{
+    constexpr int P = FG<NDIM>::P, NI = FG<NDIM>::NI;
+    T *U = (T *)a.U;
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        const int slot = a.list[item];
+        const int par = a.parent[slot];
+        if (par < 0)
+            continue;
+        const int cpos = a.blk[slot].cpos;
+        const T *pu = U + (size_t)par * NV * P;
+        T *ub = U + (size_t)slot * NV * P;
+        for (int i = threadIdx.x; i < NI; i += NTA) {
+            const int x = i % NB, y = (i / NB) % NB, z = NDIM == 3 ? i / (NB * NB) : 0;
+            T v[NV];
+            prolong_cell<NDIM, T>(pu, cpos, x, y, z, v);
+            const int c = lin<NDIM>(x, y, z);
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                ub[(size_t)k * P + c] = v[k];
+        }
+    }
+}
+
+// ---- restriction: parent cell = pairwise mean of its 2^d fine cells
+template <int NDIM, typename T>
+__global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
+{
+    constexpr int P = FG<NDIM>::P, NI = FG<NDIM>::NI;
+    T *U = (T *)a.U;
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        const int slot = a.list[item];
+        T *ub = U + (size_t)slot * NV * P;
+        for (int i = threadIdx.x; i < NI; i += NTA) {
+            const int X = i % NB, Y = (i / NB) % NB, Z = NDIM == 3 ? i / (NB * NB) : 0;
+            const int fx = 2 * X, fy = 2 * Y, fz = 2 * Z;
+            const int cbit = (fx / NB) | ((fy / NB) << 1) | (NDIM == 3 ? (fz / NB) << 2 : 0);
+            const T *cu = U + (size_t)a.children[(size_t)slot * 8 + cbit] * NV * P;
+            const int lx = fx % NB, ly = fy % NB, lz = NDIM == 3 ? fz % NB : 0;
+            const int c0 = lin<NDIM>(lx, ly, lz);
+            const int o[8] = {0, 1, PD, PD + 1, PD * PD, PD * PD + 1, PD * PD + PD, PD * PD + PD + 1};
+#pragma unroll
+            for (int k = 0; k < NV; k++) {
+                const T *q = cu + (size_t)k * P + c0;
+                T v;
+                if constexpr (NDIM == 2)
+                    v = ((q[o[0]] + q[o[1]]) + (q[o[2]] + q[o[3]])) * T(0.25);
+                else
+                    v = (((q[o[0]] + q[o[1]]) + (q[o[2]] + q[o[3]])) +
+                         ((q[o[4]] + q[o[5]]) + (q[o[6]] + q[o[7]]))) * T(0.125);
+                ub[(size_t)k * P + lin<NDIM>(X, Y, Z)] = v;
+            }
+        }
+    }
+}
+
+// ---- reflux: one workgroup per coarse leaf, its faces in a fixed order
+template <int NDIM, typename T>
+__global__ void __launch_bounds__(NTA) k_reflux(RefluxArgs a)
+{
+    constexpr int P = FG<NDIM>::P;
+    constexpr int FC = NDIM == 3 ? NB * NB : NB;
+    T *U = (T *)a.U;
+    const T *fb = (const T *)a.fbuf;
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        const int slot = a.slots[item];
+        const BlockRec br = a.blk[slot];
+        const double dtv = a.dt[br.sim].dt;
+        const double *dxp = a.lvl_dx + ((size_t)br.sim * (MAXL + 1) + br.level) * 3;
+        T *ub = U + (size_t)slot * NV * P;
+        for (int e = a.start[item]; e < a.start[item + 1]; e++) {
+            const RefluxRec r = a.recs[e];
+            const T dtdx = (T)(dtv / dxp[r.dim]);
+            const int t1 = r.dim == 0 ? 1 : 0, t2 = r.dim == 2 ? 1 : 2;
+            for (int idx = threadIdx.x; idx < FC * NV; idx += NTA) {
+                const int k = idx / FC, tt = idx - k * FC;
+                const int ta = tt % NB, tb = NDIM == 3 ? tt / NB : 0;
+                T f[4];
+                const int nf = NDIM == 3 ? 4 : 2;
+#pragma unroll
+                for (int o = 0; o < 4; o++) {
+                    if (o >= nf)
+                        break;
+                    const int fa = 2 * ta + (o & 1);
+                    const int fbb = NDIM == 3 ? 2 * tb + ((o >> 1) & 1) : 0;
+                    const int which = (fa / NB) | ((fbb / NB) << 1);
+                    const int tl = (fbb % NB) * NB + (fa % NB);
+                    f[o] = fb[((size_t)r.fb_fine[which] * NV + k) * FC + (NDIM == 3 ? tl : fa % NB)];
+                }
+                T mean;
+                if constexpr (NDIM == 3)
+                    mean = ((f[0] + f[1]) + (f[2] + f[3])) * T(0.25);
+                else
+                    mean = (f[0] + f[1]) * T(0.5);
+                const T fcv = fb[((size_t)r.fb_coarse * NV + k) * FC + tt];
+                const T delta = dtdx * (fcv - mean);
+                int loc[3] = {0, 0, 0};
+                loc[r.dim] = r.side ? NB - 1 : 0;
+                loc[t1] = ta;
+                if (t2 < NDIM)
+                    loc[t2] = tb;
+                T *cell = ub + (size_t)k * P + lin<NDIM>(loc[0], loc[1], loc[2]);
+                *cell = r.side ? *cell + delta : *cell - delta;
+            }
+            __syncthreads();  // faces of one block may share edge cells
+        }
+    }
+}
+
+// ---- CFL: per leaf, max over interior cells of max_d |v_d| + c_f,d (FP64)
+template <int NDIM, typename T>
+__global__ void __launch_bounds__(NTA) k_cfl(CflArgs a)
+{
+    constexpr int P = FG<NDIM>::P, NI = FG<NDIM>::NI;
+    __shared__ double red[NTA / 64];
+    const T *U = (const T *)a.U;
+    for (int item = blockIdx.x; item < a.nleaves; item += gridDim.x) {
+        const int slot = a.leaves[item];
+        const T *ub = U + (size_t)slot * NV * P;
+        double m = 0.0;
+        unsigned bad = 0, nonfin = 0;
+        for (int i = threadIdx.x; i < NI; i += NTA) {
+            const int x = i % NB, y = (i / NB) % NB, z = NDIM == 3 ? i / (NB * NB) : 0;
+            const int c = lin<NDIM>(x, y, z);
+            double u[NV];
+            bool fin = true;
+#pragma unroll
+            for (int k = 0; k < NV; k++) {
+                u[k] = (double)ub[(size_t)k * P + c];
+                fin = fin && isfinite(u[k]);
+            }
+            if (!fin) {
+                nonfin++;
+                continue;
+            }
+            double ir = 1.0 / u[RHO];
+            double ke = 0.5 * (u[MX] * (u[MX] * ir) + u[MY] * (u[MY] * ir) + u[MZ] * (u[MZ] * ir));
+            double me = 0.5 * (u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ]);
+            double pr = (a.gamma - 1.0) * (u[EN] - ke - me);
+            if (!(u[RHO] > 0.0) || !(pr > 0.0))
+                bad++;
+            double s = speed64<0>(a.gamma, u);
+            double s1 = speed64<1>(a.gamma, u);
+            s = s1 > s ? s1 : s;
+            if constexpr (NDIM == 3) {
+                double s2 = speed64<2>(a.gamma, u);
+                s = s2 > s ? s2 : s;
+            }
+            m = s > m ? s : m;
+        }
+        if (bad)
+            atomicAdd(&a.cnt[2], (unsigned long long)bad);
+        if (nonfin)
+            atomicAdd(&a.cnt[3], (unsigned long long)nonfin);
+        // wave64 shuffle max, then across the 4 waves through LDS
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_xor(m, off, 64);
+            m = o > m ? o : m;
+        }
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+            red[w] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r = red[0];
+            for (int i = 1; i < NTA / 64; i++)
+                r = red[i] > r ? red[i] : r;
+            a.part[item] = r;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- time-step record per simulation (one workgroup each)
+__global__ void __launch_bounds__(NTA) k_dt(DtArgs a)
+{
+    __shared__ double red[NTA / 64];
+    const int s = blockIdx.x;
+    if (s >= a.nsims)
+        return;
+    const SimRec sr = a.sims[s];
+    double m = 0.0;
+    for (int i = sr.leaf_lo + (int)threadIdx.x; i < sr.leaf_hi; i += NTA)
+        m = a.part[i] > m ? a.part[i] : m;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        double o = __shfl_xor(m, off, 64);
+        m = o > m ? o : m;
+    }
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double alpha = red[0];
+        for (int i = 1; i < NTA / 64; i++)
+            alpha = red[i] > alpha ? red[i] : alpha;
+        const double dxmin = sr.dxmin;
+        double dt = a.cfl * dxmin / (a.ndim * alpha);
+        if (a.eta > 0.0) {
+            double dr = a.cfl * dxmin * dxmin / (a.ndim * a.eta);
+            dt = dr < dt ? dr : dt;
+        }
+        map_dt r;
+        r.dt = dt;
+        r.alpha = alpha;
+        if (a.glm_mode == MAP_GLM_PAPER) {
+            r.ch = a.cfl * dxmin / dt;
+            r.damp = a.cd;
+        } else {
+            r.ch = alpha;
+            r.damp = exp(-dt * r.ch / a.cr);
+        }
+        a.dt_int[s] = r;
+        if (a.dt_out)
+            a.dt_out[s] = r;
+    }
+}
+
+// ---- FP64 totals: per leaf (fixed order), then per simulation (fixed order)
+template <int NDIM, typename T>
+__global__ void __launch_bounds__(NTA) k_totals_leaf(TotalsArgs a)
+{
+    constexpr int P = FG<NDIM>::P, NI = FG<NDIM>::NI;
+    __shared__ double red[NV][NTA];
+    const T *U = (const T *)a.U;
+    for (int item = blockIdx.x; item < a.nleaves; item += gridDim.x) {
+        const int slot = a.leaves[item];
+        const BlockRec br = a.blk[slot];
+        const double *dxp = a.lvl_dx + ((size_t)br.sim * (MAXL + 1) + br.level) * 3;
+        const double vol = dxp[0] * dxp[1] * (NDIM == 3 ? dxp[2] : 1.0);
+        const T *ub = U + (size_t)slot * NV * P;
+        double acc[NV];
+#pragma unroll
+        for (int k = 0; k < NV; k++)
+            acc[k] = 0.0;
+        for (int i = threadIdx.x; i < NI; i += NTA) {
+            const int x = i % NB, y = (i / NB) % NB, z = NDIM == 3 ? i / (NB * NB) : 0;
+            const int c = lin<NDIM>(x, y, z);
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                acc[k] += (double)ub[(size_t)k * P + c] * vol;
+        }
+#pragma unroll
+        for (int k = 0; k < NV; k++)
+            red[k][threadIdx.x] = acc[k];
+        __syncthreads();
+        for (int h = NTA / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h)
+#pragma unroll
+                for (int k = 0; k < NV; k++)
+                    red[k][threadIdx.x] += red[k][threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x < NV)
+            a.part[(size_t)item * NV + threadIdx.x] = red[threadIdx.x][0];
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(NTA) k_totals_sim(TotalsArgs a)
+{
+    __shared__ double red[NV][NTA];
+    const int s = blockIdx.x;
+    if (s >= a.nsims)
+        return;
+    const SimRec sr = a.sims[s];
+    double acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; k++)
+        acc[k] = 0.0;
+    for (int i = sr.leaf_lo + (int)threadIdx.x; i < sr.leaf_hi; i += NTA)
+#pragma unroll
+        for (int k = 0; k < NV; k++)
+            acc[k] += a.part[(size_t)i * NV + k];
+#pragma unroll
+    for (int k = 0; k < NV; k++)
+        red[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int h = NTA / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+#pragma unroll
+            for (int k = 0; k < NV; k++)
+                red[k][threadIdx.x] += red[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < NV)
+        a.out[(size_t)s * NV + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// ---- primitive (rho, v, B, p, psi) -> conserved, e = p/(gamma-1) + rho v^2/2 + B^2/2
+template <typename T>
+__global__ void __launch_bounds__(NTA) k_prim_to_cons(T *U, size_t nslots, int tile, double gamma)
+{
+    const size_t total = nslots * (size_t)tile;
+    for (size_t i = blockIdx.x * (size_t)NTA + threadIdx.x; i < total; i += (size_t)gridDim.x * NTA) {
+        const size_t s = i / tile, c = i - s * tile;
+        T *b = U + s * NV * tile + c;
+        const double r = b[RHO * (size_t)tile], vx = b[MX * (size_t)tile], vy = b[MY * (size_t)tile],
+                     vz = b[MZ * (size_t)tile];
+        const double bx = b[BX * (size_t)tile], by = b[BY * (size_t)tile], bz = b[BZ * (size_t)tile];
+        const double pr = b[EN * (size_t)tile];
+        const double e = pr / (gamma - 1.0) + 0.5 * r * (vx * vx + vy * vy + vz * vz) +
+                         0.5 * (bx * bx + by * by + bz * bz);
+        b[MX * (size_t)tile] = (T)(r * vx);
+        b[MY * (size_t)tile] = (T)(r * vy);
+        b[MZ * (size_t)tile] = (T)(r * vz);
+        b[EN * (size_t)tile] = (T)e;
+    }
+}
+
+__global__ void k_clear_u64(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0ull;
+}
+
+// ------------------------------------------------------------------ launchers
+#define DISPATCH(ndim, fp64, KER, ...)                                              \
+    do {                                                                            \
+        if (ndim == 2) {                                                            \
+            if (fp64)                                                               \
+                hipLaunchKernelGGL((KER<2, double>), __VA_ARGS__);                  \
+            else                                                                    \
+                hipLaunchKernelGGL((KER<2, float>), __VA_ARGS__);                   \
+        } else {                                                                    \
+            if (fp64)                                                               \
+                hipLaunchKernelGGL((KER<3, double>), __VA_ARGS__);                  \
+            else                                                                    \
+                hipLaunchKernelGGL((KER<3, float>), __VA_ARGS__);                   \
+        }                                                                           \
+    } while (0)
+
+int fill_blocks_per_group(int ndim) { return ndim == 3 ? FG<3>::BPW : FG<2>::BPW; }
+
+hipError_t launch_fill_copy(int ndim, bool fp64, const FillArgs &a, int grid, hipStream_t s)
+{
+    if (a.nitems <= 0)
+        return hipSuccess;
+    const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
+    DISPATCH(ndim, fp64, k_fill_copy, dim3(g), dim3(NTA), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_ghosts(int ndim, bool fp64, const FillArgs &a, hipStream_t s)
+{
+    if (a.nitems <= 0)
+        return hipSuccess;
+    DISPATCH(ndim, fp64, k_prolong_ghosts, dim3(a.nitems), dim3(NTA), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prolong_blocks(int ndim, bool fp64, const FillArgs &a, hipStream_t s)
+{
+    if (a.nitems <= 0)
+        return hipSuccess;
+    DISPATCH(ndim, fp64, k_prolong_blocks, dim3(a.nitems), dim3(NTA), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_restrict(int ndim, bool fp64, const RestrictArgs &a, hipStream_t s)
+{
+    if (a.nitems <= 0)
+        return hipSuccess;
+    DISPATCH(ndim, fp64, k_restrict, dim3(a.nitems), dim3(NTA), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reflux(int ndim, bool fp64, const RefluxArgs &a, hipStream_t s)
+{
+    if (a.nitems <= 0)
+        return hipSuccess;
+    DISPATCH(ndim, fp64, k_reflux, dim3(a.nitems), dim3(NTA), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cfl(int ndim, bool fp64, const CflArgs &a, hipStream_t s)
+{
+    if (a.nleaves <= 0)
+        return hipSuccess;
+    DISPATCH(ndim, fp64, k_cfl, dim3(a.nleaves), dim3(NTA), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt(const DtArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dt, dim3(a.nsims), dim3(NTA), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(int ndim, bool fp64, const TotalsArgs &a, hipStream_t s)
+{
+    if (a.nleaves > 0)
+        DISPATCH(ndim, fp64, k_totals_leaf, dim3(a.nleaves), dim3(NTA), 0, s, a);
+    hipLaunchKernelGGL(k_totals_sim, dim3(a.nsims), dim3(NTA), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prim_to_cons(bool fp64, void *U, size_t nslots, int tile, double gamma,
+                               hipStream_t s)
+{
+    size_t total = nslots * (size_t)tile;
+    int g = (int)((total + NTA - 1) / NTA);
+    if (g > 65536)
+        g = 65536;
+    if (g < 1)
+        g = 1;
+    if (fp64)
+        hipLaunchKernelGGL(k_prim_to_cons<double>, dim3(g), dim3(NTA), 0, s, (double *)U, nslots,
+                           tile, gamma);
+    else
+        hipLaunchKernelGGL(k_prim_to_cons<float>, dim3(g), dim3(NTA), 0, s, (float *)U, nslots, tile,
+                           gamma);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_clear_u64, dim3((n + 63) / 64), dim3(64), 0, s, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace mapk

@@ -1,0 +1,518 @@
+// k_step_lf.hip -- the TVD-LF block update (paper Sec. 3.2, all directions
+// together as in Sec. 3.7) with the EGLM source terms (Sec. 2), uniform
+// resistivity (Sec. 3.5) and exact psi damping, for every leaf of a work list.
+//
+// Layout and schedule (gfx950): each workgroup owns whole blocks.  Threads own
+// the columns of the block's padded cross-section (x in 2-D, x-y in 3-D) and
+// march along the last axis (y in 2-D, z in 3-D), one plane per iteration:
+//   * the march-axis neighbours of a cell (slopes, the half-step flux, the
+//     face between planes, source and resistive differences) stay in
+//     registers of the owning thread;
+//   * in-plane neighbours are exchanged through LDS one plane at a time
+//     (state, right face states, face fluxes, eta J), so LDS holds one plane
+//     of a block instead of the whole padded tile (a 20^3 x 9 FP32 tile would
+//     not fit in 160 KB);
+//   * each face flux is evaluated once; the next plane is prefetched from
+//     HBM while the current one is processed; every HBM access is a
+//     contiguous row of the structure-of-arrays tile.
+// 2-D workgroups hold 12 blocks (240 columns), 3-D workgroups one block
+// (400 columns, 7 waves).  A persistent grid strides over the work list.
+#include <type_traits>
+
+#include "kernels.hpp"
+#include "physics.hpp"
+
+namespace mapk {
+
+template <int NDIM>
+struct SG;
+template <>
+struct SG<2> {
+    static constexpr int XS = PD, BPW = 12, NT = 256;
+};
+template <>
+struct SG<3> {
+    static constexpr int XS = PD * PD, BPW = 1, NT = 448;
+};
+
+template <int D, typename T, bool MIXED>
+__device__ __forceinline__ void rusanov(const Phys<T, MIXED> &ph, const T L[NV], const T R[NV],
+                                        T ch, T ch2, T f[NV])
+{
+    T FL[NV], FR[NV];
+    T sL = ph.template flux<D, true>(L, ch2, FL);
+    T sR = ph.template flux<D, true>(R, ch2, FR);
+    T al = sL > sR ? sL : sR;
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+        T ak = (k == BX + D || k == PSI) ? ch : al;
+        f[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * ak * (R[k] - L[k]);
+    }
+}
+
+template <int NDIM, typename T, bool MIXED, bool RESIST>
+__global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
+{
+    constexpr int XS = SG<NDIM>::XS, BPW = SG<NDIM>::BPW, DIN = NDIM - 1, MD = NDIM - 1;
+    constexpr int P = XS * PD;
+    constexpr int FC = NDIM == 3 ? NB * NB : NB;
+    constexpr int SY = PD;  // in-plane y stride (3-D)
+    __shared__ T su[BPW * NV * XS];
+    __shared__ T srf[BPW * DIN * NV * XS];
+    __shared__ T sj[RESIST ? BPW * 5 * XS : 1];
+
+    const int t = threadIdx.x;
+    const int lb = t / XS;
+    const int q = t - lb * XS;
+    const bool lane = lb < BPW;
+    const int qx = q % PD - NG;
+    const int qy = NDIM == 3 ? q / PD - NG : 0;
+    const bool xE = qx >= -1 && qx <= NB, xI = qx >= 0 && qx < NB;
+    const bool yE = NDIM == 2 || (qy >= -1 && qy <= NB);
+    const bool yI = NDIM == 2 || (qy >= 0 && qy < NB);
+    const bool inE = lane && xE && yE;
+    const bool inI = lane && xI && yI;
+
+    Phys<T, MIXED> ph;
+    ph.gamma = (T)a.gamma;
+    ph.gm1 = (T)(a.gamma - 1.0);
+    ph.gm1d = a.gamma - 1.0;
+    const T *Uin = (const T *)a.Uin;
+    T *Uout = (T *)a.Uout;
+    T *fbuf = (T *)a.fbuf;
+    const int lim = a.limiter;
+
+    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+        const int li = item * BPW + lb;
+        const bool has = lane && li < a.nleaves;
+        const int slot = has ? a.leaves[li] : 0;
+        const BlockRec br = a.blk[slot];
+        const map_dt rec = a.dt[br.sim];
+        const double *dxp = a.lvl_dx + ((size_t)br.sim * (MAXL + 1) + br.level) * 3;
+        T dtdx[NDIM], hdt[NDIM], i2d[NDIM];
+#pragma unroll
+        for (int d = 0; d < NDIM; d++) {
+            double r = rec.dt / dxp[d];
+            dtdx[d] = (T)r;
+            hdt[d] = (T)(0.5 * r);
+            i2d[d] = (T)(0.5 / dxp[d]);
+        }
+        const T dt = (T)rec.dt, ch = (T)rec.ch, ch2 = (T)(rec.ch * rec.ch), damp = (T)rec.damp;
+        const T eta = (T)a.eta;
+        const T *ub = Uin + (size_t)slot * NV * P;
+        T *ob = Uout + (size_t)slot * NV * P;
+
+        auto load = [&](T(&dst)[NV], int k) {
+            if (has) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    dst[v] = ub[(size_t)v * P + (k + NG) * XS + q];
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    dst[v] = T(0);
+                dst[RHO] = T(1);
+                dst[EN] = T(4);
+            }
+        };
+
+        T um[NV], u0[NV], up[NV], upp[NV];
+        load(um, -2);
+        load(u0, -1);
+        load(up, 0);
+        T Lm_prev[NV], fm_prev[NV], w_prev[NV], s_prev[4];
+        T rin_prev[4], jm1[3], jm2[3];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            Lm_prev[v] = T(0);
+            fm_prev[v] = T(0);
+            w_prev[v] = T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            s_prev[i] = T(0);
+            rin_prev[i] = T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
+            jm1[i] = T(0);
+            jm2[i] = T(0);
+        }
+
+        for (int k = -1; k <= NB; ++k) {
+            if (k + 2 <= NB + 1)
+                load(upp, k + 2);
+            // ---- (A) publish plane k
+            if (lane) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    su[(lb * NV + v) * XS + q] = u0[v];
+            }
+            __syncthreads();
+
+            T Lin[DIN][NV], Lm[NV], Rm[NV];
+            T src[4] = {T(0), T(0), T(0), T(0)};
+            T jc[3] = {T(0), T(0), T(0)};
+            const bool kI = k >= 0 && k < NB;
+            if (inE) {
+                // slopes from the old-time differences (limiter1)
+                T dl[NDIM][NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    const T *row = su + (lb * NV + v) * XS;
+                    dl[0][v] = limiter(lim, u0[v] - row[q - 1], row[q + 1] - u0[v]);
+                    if constexpr (NDIM == 3)
+                        dl[1][v] = limiter(lim, u0[v] - row[q - SY], row[q + SY] - u0[v]);
+                    dl[MD][v] = limiter(lim, u0[v] - um[v], up[v] - u0[v]);
+                }
+                bool ok = true;
+#pragma unroll
+                for (int d = 0; d < NDIM; d++) {
+                    T s1[NV], s2[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        s1[v] = u0[v] + T(0.5) * dl[d][v];
+                        s2[v] = u0[v] - T(0.5) * dl[d][v];
+                    }
+                    bool a1 = ph.admissible(s1), a2 = ph.admissible(s2);
+                    ok = ok && a1 && a2;
+                }
+                if (!ok) {
+#pragma unroll
+                    for (int d = 0; d < NDIM; d++)
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            dl[d][v] = T(0);
+                    if (has)
+                        atomicAdd(&a.cnt[0], 1ull);
+                }
+                // half-step predictor: u~ = u - dt/(2dx) sum_d [f(u + D/2) - f(u - D/2)]
+                T acc[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    acc[v] = T(0);
+                auto pred = [&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    T sp[NV], sm[NV], fp[NV], fm[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        sp[v] = u0[v] + T(0.5) * dl[d][v];
+                        sm[v] = u0[v] - T(0.5) * dl[d][v];
+                    }
+                    ph.template flux<d, false>(sp, ch2, fp);
+                    ph.template flux<d, false>(sm, ch2, fm);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        acc[v] += hdt[d] * (fp[v] - fm[v]);
+                };
+                pred(std::integral_constant<int, 0>{});
+                pred(std::integral_constant<int, 1>{});
+                if constexpr (NDIM == 3)
+                    pred(std::integral_constant<int, 2>{});
+                T ut[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    ut[v] = u0[v] - acc[v];
+                // face states with the old-time slopes (limiter2); a state with
+                // rho <= 0 or p <= 0 is replaced by the cell's u~
+                const int qc[3] = {qx, NDIM == 3 ? qy : k, k};
+#pragma unroll
+                for (int d = 0; d < NDIM; d++) {
+                    T L[NV], R[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        L[v] = ut[v] + T(0.5) * dl[d][v];
+                        R[v] = ut[v] - T(0.5) * dl[d][v];
+                    }
+                    bool others = true;
+#pragma unroll
+                    for (int e = 0; e < NDIM; e++)
+                        if (e != d)
+                            others = others && qc[e] >= 0 && qc[e] < NB;
+                    if (!ph.admissible(L)) {
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            L[v] = ut[v];
+                        if (has && others && qc[d] < NB)
+                            atomicAdd(&a.cnt[1], 1ull);
+                    }
+                    if (!ph.admissible(R)) {
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            R[v] = ut[v];
+                        if (has && others && qc[d] >= 0)
+                            atomicAdd(&a.cnt[1], 1ull);
+                    }
+                    if (d < DIN) {
+#pragma unroll
+                        for (int v = 0; v < NV; v++) {
+                            srf[((lb * DIN + d) * NV + v) * XS + q] = R[v];
+                            Lin[d < DIN ? d : 0][v] = L[v];
+                        }
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < NV; v++) {
+                            Lm[v] = L[v];
+                            Rm[v] = R[v];
+                        }
+                    }
+                }
+                // EGLM sources from central differences of u^n
+                if (a.eglm && inI && kI) {
+                    const T *bx = su + (lb * NV + BX) * XS, *by = su + (lb * NV + BY) * XS;
+                    const T *ps = su + (lb * NV + PSI) * XS;
+                    T divb = (bx[q + 1] - bx[q - 1]) * i2d[0];
+                    T bgp = u0[BX] * ((ps[q + 1] - ps[q - 1]) * i2d[0]);
+                    if constexpr (NDIM == 3) {
+                        divb += (by[q + SY] - by[q - SY]) * i2d[1];
+                        bgp += u0[BY] * ((ps[q + SY] - ps[q - SY]) * i2d[1]);
+                    }
+                    divb += (up[BX + MD] - um[BX + MD]) * i2d[MD];
+                    bgp += u0[BX + MD] * ((up[PSI] - um[PSI]) * i2d[MD]);
+                    src[0] = divb * u0[BX];
+                    src[1] = divb * u0[BY];
+                    src[2] = divb * u0[BZ];
+                    src[3] = bgp;
+                }
+                // resistivity: eta J and eta (J x B) on this plane
+                if constexpr (RESIST) {
+                    const T *bx = su + (lb * NV + BX) * XS, *by = su + (lb * NV + BY) * XS;
+                    const T *bz = su + (lb * NV + BZ) * XS;
+                    T jx, jy, jz;
+                    if constexpr (NDIM == 3) {
+                        T dyBz = (bz[q + SY] - bz[q - SY]) * i2d[1];
+                        T dzBy = (up[BY] - um[BY]) * i2d[2];
+                        T dzBx = (up[BX] - um[BX]) * i2d[2];
+                        T dxBz = (bz[q + 1] - bz[q - 1]) * i2d[0];
+                        T dxBy = (by[q + 1] - by[q - 1]) * i2d[0];
+                        T dyBx = (bx[q + SY] - bx[q - SY]) * i2d[1];
+                        jx = dyBz - dzBy;
+                        jy = dzBx - dxBz;
+                        jz = dxBy - dyBx;
+                    } else {
+                        T dyBz = (up[BZ] - um[BZ]) * i2d[1];
+                        T dxBz = (bz[q + 1] - bz[q - 1]) * i2d[0];
+                        T dxBy = (by[q + 1] - by[q - 1]) * i2d[0];
+                        T dyBx = (up[BX] - um[BX]) * i2d[1];
+                        jx = dyBz;
+                        jy = -dxBz;
+                        jz = dxBy - dyBx;
+                    }
+                    T ejx = eta * jx, ejy = eta * jy, ejz = eta * jz;
+                    T qx_ = eta * (jz * u0[BY] - jy * u0[BZ]);
+                    T qy_ = eta * (jx * u0[BZ] - jz * u0[BX]);
+                    T qz_ = eta * (jy * u0[BX] - jx * u0[BY]);
+                    T *J = sj + lb * 5 * XS;
+                    J[0 * XS + q] = ejx;
+                    J[1 * XS + q] = ejy;
+                    J[2 * XS + q] = ejz;
+                    J[3 * XS + q] = qx_;
+                    J[4 * XS + q] = qy_;
+                    if constexpr (NDIM == 3) {
+                        jc[0] = ejx;
+                        jc[1] = ejy;
+                        jc[2] = qz_;
+                    } else {
+                        jc[0] = ejx;
+                        jc[1] = ejz;
+                        jc[2] = qy_;
+                    }
+                }
+            }
+            __syncthreads();  // (B) right face states and eta J published
+
+            // ---- fluxes of the in-plane faces of plane k and of the face k-1/2
+            T fin[DIN][NV];
+            bool dof[DIN];
+            T rin[4] = {T(0), T(0), T(0), T(0)};
+            dof[0] = kI && lane && qx >= -1 && qx < NB && yI;
+            if constexpr (NDIM == 3)
+                dof[DIN - 1] = kI && lane && qy >= -1 && qy < NB && xI;
+            if (dof[0]) {
+                T R[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    R[v] = srf[((lb * DIN + 0) * NV + v) * XS + q + 1];
+                rusanov<0>(ph, Lin[0], R, ch, ch2, fin[0]);
+            }
+            if constexpr (NDIM == 3) {
+                if (dof[1]) {
+                    T R[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        R[v] = srf[((lb * DIN + 1) * NV + v) * XS + q + SY];
+                    rusanov<1>(ph, Lin[1], R, ch, ch2, fin[1]);
+                }
+            }
+            if constexpr (RESIST) {
+                if (inI && kI) {
+                    const T *J = sj + lb * 5 * XS;
+                    const T *J0 = J, *J1 = J + XS, *J2 = J + 2 * XS, *Q0 = J + 3 * XS, *Q1 = J + 4 * XS;
+                    if constexpr (NDIM == 3) {
+                        rin[0] = -((J2[q + SY] - J2[q - SY]) * i2d[1]);
+                        rin[1] = (J2[q + 1] - J2[q - 1]) * i2d[0];
+                        rin[2] = (J0[q + SY] - J0[q - SY]) * i2d[1] - (J1[q + 1] - J1[q - 1]) * i2d[0];
+                        rin[3] = (Q0[q + 1] - Q0[q - 1]) * i2d[0] + (Q1[q + SY] - Q1[q - SY]) * i2d[1];
+                    } else {
+                        rin[0] = (J2[q + 1] - J2[q - 1]) * i2d[0];
+                        rin[1] = (J1[q + 1] - J1[q - 1]) * i2d[0];
+                        rin[2] = (Q0[q + 1] - Q0[q - 1]) * i2d[0];
+                    }
+                }
+            }
+            const bool dom = inI && k >= 0;
+            T fmc[NV];
+            if (dom)
+                rusanov<MD>(ph, Lm_prev, Rm, ch, ch2, fmc);
+            __syncthreads();  // (C) all reads of the right face states done
+#pragma unroll
+            for (int d = 0; d < DIN; d++)
+                if (dof[d]) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        srf[((lb * DIN + d) * NV + v) * XS + q] = fin[d][v];
+                }
+            // fluxes of block faces shared with another level (reflux)
+            if (has) {
+#pragma unroll
+                for (int d = 0; d < DIN; d++) {
+                    if (!dof[d])
+                        continue;
+                    const int qd = d == 0 ? qx : qy;
+                    const int side = qd == -1 ? 0 : (qd == NB - 1 ? 1 : -1);
+                    if (side < 0)
+                        continue;
+                    const int fb = a.fbidx[(size_t)slot * 6 + 2 * d + side];
+                    if (fb < 0)
+                        continue;
+                    int tt;
+                    if constexpr (NDIM == 3)
+                        tt = (d == 0 ? qy : qx) + NB * k;
+                    else
+                        tt = k;
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        fbuf[((size_t)fb * NV + v) * FC + tt] = fin[d][v];
+                }
+                if (dom && (k == 0 || k == NB)) {
+                    const int fb = a.fbidx[(size_t)slot * 6 + 2 * MD + (k == NB ? 1 : 0)];
+                    if (fb >= 0) {
+                        const int tt = NDIM == 3 ? qx + NB * qy : qx;
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            fbuf[((size_t)fb * NV + v) * FC + tt] = fmc[v];
+                    }
+                }
+            }
+            __syncthreads();  // (D) in-plane face fluxes published
+
+            T w_cur[NV];
+            if (inI && kI) {
+#pragma unroll
+                for (int v = 0; v < NV; v++) {
+                    T acc = dtdx[0] * (fin[0][v] - srf[((lb * DIN + 0) * NV + v) * XS + q - 1]);
+                    if constexpr (NDIM == 3)
+                        acc += dtdx[1] * (fin[1][v] - srf[((lb * DIN + 1) * NV + v) * XS + q - SY]);
+                    w_cur[v] = u0[v] - acc;
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    w_cur[v] = T(0);
+            }
+            // ---- finalise plane k-1: march-axis flux difference, sources,
+            //      resistivity, psi damping (MHD-5 integrated exactly)
+            if (dom && k >= 1 && has) {
+                T o[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    o[v] = w_prev[v] - dtdx[MD] * (fmc[v] - fm_prev[v]);
+                if (a.eglm) {
+                    o[MX] = o[MX] - dt * s_prev[0];
+                    o[MY] = o[MY] - dt * s_prev[1];
+                    o[MZ] = o[MZ] - dt * s_prev[2];
+                    o[EN] = o[EN] - dt * s_prev[3];
+                }
+                if constexpr (RESIST) {
+                    T rx, ry, rz, re;
+                    if constexpr (NDIM == 3) {
+                        rx = (jc[1] - jm2[1]) * i2d[2] + rin_prev[0];
+                        ry = rin_prev[1] - (jc[0] - jm2[0]) * i2d[2];
+                        rz = rin_prev[2];
+                        re = rin_prev[3] + (jc[2] - jm2[2]) * i2d[2];
+                    } else {
+                        rx = -((jc[1] - jm2[1]) * i2d[1]);
+                        ry = rin_prev[0];
+                        rz = (jc[0] - jm2[0]) * i2d[1] - rin_prev[1];
+                        re = rin_prev[2] + (jc[2] - jm2[2]) * i2d[1];
+                    }
+                    o[BX] = o[BX] + dt * rx;
+                    o[BY] = o[BY] + dt * ry;
+                    o[BZ] = o[BZ] + dt * rz;
+                    o[EN] = o[EN] + dt * re;
+                }
+                o[PSI] = o[PSI] * damp;
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    ob[(size_t)v * P + (k - 1 + NG) * XS + q] = o[v];
+            }
+            // ---- shift the march-axis registers
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                fm_prev[v] = dom ? fmc[v] : T(0);
+                Lm_prev[v] = inE ? Lm[v] : T(0);
+                w_prev[v] = w_cur[v];
+                um[v] = u0[v];
+                u0[v] = up[v];
+                up[v] = upp[v];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                s_prev[i] = src[i];
+                rin_prev[i] = rin[i];
+            }
+#pragma unroll
+            for (int i = 0; i < 3; i++) {
+                jm2[i] = jm1[i];
+                jm1[i] = jc[i];
+            }
+        }
+        __syncthreads();  // LDS reuse by the next work item
+    }
+}
+
+template <int NDIM, typename T, bool MIXED, bool RESIST>
+static hipError_t launch_one(const StepArgs &a, int grid, hipStream_t s)
+{
+    if (a.nitems <= 0)
+        return hipSuccess;
+    int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
+    hipLaunchKernelGGL((k_step_lf<NDIM, T, MIXED, RESIST>), dim3(g), dim3(SG<NDIM>::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+int step_blocks_per_group(int ndim, int scheme)
+{
+    if (scheme == MAP_MMC)
+        return 1;
+    return ndim == 3 ? SG<3>::BPW : SG<2>::BPW;
+}
+
+hipError_t launch_step_lf(int ndim, bool fp64, bool resist, const StepArgs &a, int grid,
+                          hipStream_t s)
+{
+    if (ndim == 2) {
+        if (fp64)
+            return resist ? launch_one<2, double, false, true>(a, grid, s)
+                          : launch_one<2, double, false, false>(a, grid, s);
+        return resist ? launch_one<2, float, true, true>(a, grid, s)
+                      : launch_one<2, float, true, false>(a, grid, s);
+    }
+    if (fp64)
+        return resist ? launch_one<3, double, false, true>(a, grid, s)
+                      : launch_one<3, double, false, false>(a, grid, s);
+    return resist ? launch_one<3, float, true, true>(a, grid, s)
+                  : launch_one<3, float, true, false>(a, grid, s);
+}
+
+}  // namespace mapk

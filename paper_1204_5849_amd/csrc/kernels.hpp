@@ -1,0 +1,103 @@
+// kernels.hpp -- kernel argument records and launch entry points (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "map_internal.hpp"
+
+namespace mapk {
+
+struct StepArgs {
+    const void *Uin;
+    void *Uout;
+    const int32_t *leaves;  // leaf slots processed by this launch
+    int nleaves;
+    int nitems;             // work items (groups of blocks per workgroup)
+    const BlockRec *blk;
+    const map_dt *dt;
+    const double *lvl_dx;
+    const int32_t *fbidx;
+    void *fbuf;
+    unsigned long long *cnt;
+    double gamma, eta;
+    int eglm, limiter;
+};
+
+struct FillArgs {
+    void *U;
+    const Desc *desc;
+    const BlockRec *blk;
+    const int32_t *parent;
+    const int32_t *list;   // prolongation: slots; copy: unused
+    int slot_base, slot_end, nitems;
+};
+
+struct RestrictArgs {
+    void *U;
+    const int32_t *list;
+    const int32_t *children;
+    int nitems;
+};
+
+struct RefluxArgs {
+    void *U;
+    const int32_t *slots;
+    const int32_t *start;
+    const RefluxRec *recs;
+    const BlockRec *blk;
+    const map_dt *dt;
+    const double *lvl_dx;
+    const void *fbuf;
+    int nitems;
+};
+
+struct CflArgs {
+    const void *U;
+    const int32_t *leaves;
+    int nleaves;
+    double *part;
+    unsigned long long *cnt;
+    double gamma;
+};
+
+struct DtArgs {
+    const double *part;
+    const SimRec *sims;
+    map_dt *dt_int;
+    map_dt *dt_out;  // optional copy
+    int nsims, ndim, glm_mode;
+    double cfl, cd, cr, eta;
+};
+
+struct TotalsArgs {
+    const void *U;
+    const int32_t *leaves;
+    int nleaves;
+    const BlockRec *blk;
+    const double *lvl_dx;
+    double *part;
+    const SimRec *sims;
+    double *out;
+    int nsims, ndim;
+};
+
+// launchers (defined in the .hip files); return hipError_t of the launch
+hipError_t launch_step_lf(int ndim, bool fp64, bool resist, const StepArgs &a, int grid,
+                          hipStream_t s);
+hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double alpha_unused, int grid,
+                           hipStream_t s);
+int step_blocks_per_group(int ndim, int scheme);
+hipError_t launch_fill_copy(int ndim, bool fp64, const FillArgs &a, int grid, hipStream_t s);
+int fill_blocks_per_group(int ndim);
+hipError_t launch_prolong_ghosts(int ndim, bool fp64, const FillArgs &a, hipStream_t s);
+hipError_t launch_prolong_blocks(int ndim, bool fp64, const FillArgs &a, hipStream_t s);
+hipError_t launch_restrict(int ndim, bool fp64, const RestrictArgs &a, hipStream_t s);
+hipError_t launch_reflux(int ndim, bool fp64, const RefluxArgs &a, hipStream_t s);
+hipError_t launch_cfl(int ndim, bool fp64, const CflArgs &a, hipStream_t s);
+hipError_t launch_dt(const DtArgs &a, hipStream_t s);
+hipError_t launch_totals(int ndim, bool fp64, const TotalsArgs &a, hipStream_t s);
+hipError_t launch_prim_to_cons(bool fp64, void *U, size_t ncell_per_var_total, int tile,
+                               double gamma, hipStream_t s);
+hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
+
+}  // namespace mapk

@@ -1,0 +1,157 @@
+// physics.hpp -- device-side pointwise EGLM-MHD physics: pressure, fluxes,
+// fast speeds and limiters (paper Sec. 2 and Sec. 3).  T = double for the
+// FP64 path; T = float with MIXED = true for the FP32 path, where the
+// pressure is recovered in FP64 from the FP32 conserved variables (the
+// products of FP32 numbers are exact in FP64, so the cancellation in
+// e - rho v^2/2 - B^2/2 at low plasma beta costs no precision).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "map_internal.hpp"
+
+namespace mapk {
+
+template <typename T>
+struct Num;
+
+template <>
+struct Num<double> {
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+};
+
+template <>
+struct Num<float> {
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+};
+
+template <typename T>
+__device__ __forceinline__ T sgn_of(T a)
+{
+    return a > T(0) ? T(1) : (a < T(0) ? T(-1) : T(0));
+}
+
+// minmod(a,b) = sgn(a) max(0, min(|a|, sgn(a) b))  (eq. minmod)
+template <typename T>
+__device__ __forceinline__ T lim_minmod(T a, T b)
+{
+    T s = sgn_of(a);
+    T m = fabs(a);
+    T t = s * b;
+    m = t < m ? t : m;
+    m = m < T(0) ? T(0) : m;
+    return s * m;
+}
+
+// limiter selected at run time (uniform across the launch):
+// minmod, van Leer (ab + |ab|)/(a + b), or the literal flux limiter of
+// Sec. 3.1 in ratio-free form phi(a/b) b
+template <typename T>
+__device__ __forceinline__ T limiter(int kind, T a, T b)
+{
+    if (kind == MAP_MINMOD)
+        return lim_minmod(a, b);
+    if (kind == MAP_VANLEER) {
+        T ab = a * b;
+        return ab <= T(0) ? T(0) : Num<T>::div(ab + fabs(ab), a + b);
+    }
+    return fabs(a) <= fabs(b) ? a : b;
+}
+
+template <typename T, bool MIXED>
+struct Phys {
+    T gamma, gm1;
+    double gm1d;
+
+    // p = (gamma - 1)(e - rho v^2/2 - B^2/2); ir = 1/rho, v = m ir
+    __device__ __forceinline__ T pressure(const T u[NV], T ir, T vx, T vy, T vz, T me) const
+    {
+        if constexpr (MIXED) {
+            double r = (double)ir;
+            r = r * (2.0 - (double)u[RHO] * r);  // one Newton step on 1/rho
+            double m2 = (double)u[MX] * (double)u[MX] + (double)u[MY] * (double)u[MY] +
+                        (double)u[MZ] * (double)u[MZ];
+            double b2 = (double)u[BX] * (double)u[BX] + (double)u[BY] * (double)u[BY] +
+                        (double)u[BZ] * (double)u[BZ];
+            return (T)(gm1d * (((double)u[EN] - 0.5 * m2 * r) - 0.5 * b2));
+        } else {
+            T ke = T(0.5) * (u[MX] * vx + u[MY] * vy + u[MZ] * vz);
+            return gm1 * (u[EN] - ke - me);
+        }
+    }
+
+    __device__ __forceinline__ bool admissible(const T u[NV]) const
+    {
+        if (!(u[RHO] > T(0)))
+            return false;
+        T ir = Num<T>::rcp(u[RHO]);
+        T vx = u[MX] * ir, vy = u[MY] * ir, vz = u[MZ] * ir;
+        T me = T(0.5) * (u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ]);
+        return pressure(u, ir, vx, vy, vz, me) > T(0);
+    }
+
+    // EGLM flux along D (MHD-1..MHD-5); returns |v_D| + c_f,D if SPEED
+    template <int D, bool SPEED>
+    __device__ __forceinline__ T flux(const T u[NV], T ch2, T f[NV]) const
+    {
+        T ir = Num<T>::rcp(u[RHO]);
+        T v[3] = {u[MX] * ir, u[MY] * ir, u[MZ] * ir};
+        const T B[3] = {u[BX], u[BY], u[BZ]};
+        T bb = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+        T me = T(0.5) * bb;
+        T pr = pressure(u, ir, v[0], v[1], v[2], me);
+        T pt = pr + me;
+        T vd = v[D], Bd = B[D];
+        T vb = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
+        f[RHO] = u[MX + D];
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            f[MX + j] = u[MX + j] * vd - B[j] * Bd;
+        f[MX + D] = f[MX + D] + pt;
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            f[BX + j] = B[j] * vd - Bd * v[j];
+        f[BX + D] = u[PSI];
+        f[EN] = (u[EN] + pt) * vd - Bd * vb;
+        f[PSI] = ch2 * Bd;
+        if constexpr (SPEED) {
+            T a2 = gamma * pr * ir;
+            T b2 = bb * ir;
+            T s = a2 + b2;
+            T disc = s * s - T(4) * a2 * (Bd * Bd) * ir;
+            disc = disc < T(0) ? T(0) : disc;
+            T cf2 = T(0.5) * (s + Num<T>::sqrt_(disc));
+            cf2 = cf2 < T(0) ? T(0) : cf2;
+            return fabs(vd) + Num<T>::sqrt_(cf2);
+        } else {
+            return T(0);
+        }
+    }
+};
+
+// |v_d| + c_f,d evaluated in FP64 from a state of either precision (CFL pass)
+template <int D>
+__device__ __forceinline__ double speed64(double gamma, const double u[NV])
+{
+    double ir = 1.0 / u[RHO];
+    double vx = u[MX] * ir, vy = u[MY] * ir, vz = u[MZ] * ir;
+    double ke = 0.5 * (u[MX] * vx + u[MY] * vy + u[MZ] * vz);
+    double me = 0.5 * (u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ]);
+    double pr = (gamma - 1.0) * (u[EN] - ke - me);
+    double a2 = gamma * pr * ir;
+    double bb = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
+    double b2 = bb * ir;
+    double s = a2 + b2;
+    double disc = s * s - 4.0 * a2 * (u[BX + D] * u[BX + D]) * ir;
+    disc = disc < 0.0 ? 0.0 : disc;
+    double cf2 = 0.5 * (s + sqrt(disc));
+    cf2 = cf2 < 0.0 ? 0.0 : cf2;
+    double vd = D == 0 ? vx : (D == 1 ? vy : vz);
+    return fabs(vd) + sqrt(cf2);
+}
+
+}  // namespace mapk

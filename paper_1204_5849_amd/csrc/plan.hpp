@@ -1,0 +1,58 @@
+// plan.hpp -- host-side context: the validated block tree in Morton order and
+// the tables the kernels read ("neighbour statistics" of the paper, Sec. 4.2).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "map_internal.hpp"
+
+struct map_ctx {
+    map_params p{};
+    int nd = 2;
+    int tile = 0;                          // padded cells per variable
+    int nslots = 0, nleaves = 0, lmax = 1;
+    std::vector<map_sim_desc> sims;
+    std::vector<int32_t> slot_of_key;      // input index -> slot
+    std::vector<map_block_key> key;        // by slot
+    std::vector<mapk::BlockRec> blk;       // by slot
+    std::vector<int32_t> parent;           // by slot, -1 at level 1
+    std::vector<int32_t> children;         // [slot][8], -1 if none
+    std::vector<mapk::Desc> desc;          // [slot][27]
+    std::vector<int32_t> fbidx;            // [slot][6], -1 if none
+    std::vector<int32_t> leaves;           // leaf slots in Morton order
+    std::vector<mapk::SimRec> simrec;
+    std::vector<double> lvl_dx;            // [sim][MAXL + 1][3]
+    std::vector<int32_t> restrict_list;    // parent slots, grouped by level
+    std::vector<int> restrict_off;         // [lmax + 1] offsets by level
+    std::vector<int32_t> prolong_list;     // slots with prolongated ghosts, by level
+    std::vector<int> prolong_off;          // [lmax + 2]
+    std::vector<int32_t> reflux_slots;     // coarse leaves with reflux faces
+    std::vector<int32_t> reflux_start;     // [n + 1] into reflux_recs
+    std::vector<mapk::RefluxRec> reflux_recs;
+    int nfb = 0;                           // face buffers
+
+    // device binding
+    mapk::WsLayout ws{};
+    char *wsp = nullptr;
+    bool bound = false;
+    size_t word = 8;
+
+    // launch configuration
+    int launch_mode = MAP_LAUNCH_BATCHED;
+    int grid_step = 0, grid_fill = 0;
+
+    // captured cycle
+    void *graph_exec = nullptr;  // hipGraphExec_t
+    void *graph_U = nullptr;
+    void *cap_stream = nullptr;  // hipStream_t used for capture
+
+    size_t face_cells() const { return nd == 3 ? (size_t)mapk::NB * mapk::NB : (size_t)mapk::NB; }
+};
+
+// builds everything above except the device binding; returns MAP_OK,
+// MAP_EINVAL or MAP_ETREE with a message in `err`
+map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_sim_desc *sims,
+                          int nblocks, const map_block_key *keys, std::string &err);
+void map_plan_layout(map_ctx *c);
+uint64_t map_morton3(uint32_t x, uint32_t y, uint32_t z);

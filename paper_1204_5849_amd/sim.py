@@ -1,0 +1,139 @@
+"""Device-side driver of one block tree: torch owns the state, workspace and
+stream; every stage runs through the C ABI in native.py.
+
+    sim = Simulation(workload, device="cuda:0")
+    sim.load_initial()            # primitives -> slots, conversion, restrict, fill
+    sim.advance(10)               # or sim.graph_run(10)
+    U = sim.state_by_key()        # float64 numpy [nblocks, 9, pz, py, px], input key order
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import native as N
+from .workloads import Workload
+
+NB, NG, PD, NV = 16, 2, 20, 9
+
+
+class Simulation:
+    def __init__(self, wl: Workload, device="cuda:0", stream: torch.cuda.Stream | None = None,
+                 precision: str | None = None, launch: str = "batched"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("Simulation needs a HIP device")
+        self.wl = wl
+        self.device = torch.device(device)
+        self.precision = precision or wl.precision
+        self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
+        self.params = N.make_params(wl.ndim, precision=self.precision, scheme=wl.scheme,
+                                    limiter=wl.limiter, glm_mode=wl.glm_mode,
+                                    eglm_sources=wl.eglm_sources, gamma=wl.gamma, cfl=wl.cfl,
+                                    cd=wl.cd, cr=wl.cr, eta=wl.eta)
+        self.ctx = N.map_init_blocks(self.params, wl.sims, wl.keys)
+        self.sizes, self.slot_of_key = N.map_query(self.ctx)
+        self.nslots = self.sizes.nblocks
+        self.tile = self.sizes.tile_cells
+        self.stream = stream or torch.cuda.Stream(device=self.device)
+        pz = PD if wl.ndim == 3 else 1
+        self.shape = (self.nslots, NV, pz, PD, PD)
+        with torch.cuda.device(self.device):
+            self.U = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
+            self.ws = torch.zeros(self.sizes.workspace_bytes + 256, dtype=torch.uint8,
+                                  device=self.device)
+            self.dt = torch.zeros((len(wl.sims), 4), dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize(self.device)
+        base = self.ws.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        N.map_bind_workspace(self.ctx, self._ws_ptr, self.sizes.workspace_bytes, self.sp)
+        if launch == "per_block":
+            N.map_set_launch(self.ctx, N.MAP_LAUNCH_PER_BLOCK)
+
+    @property
+    def sp(self):
+        return self.stream.cuda_stream
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            N.map_destroy(ctx)
+            self.ctx = None
+
+    # ---------------------------------------------------------------- data
+    def interior_view(self):
+        if self.wl.ndim == 3:
+            return self.U[:, :, NG:-NG, NG:-NG, NG:-NG]
+        return self.U[:, :, :, NG:-NG, NG:-NG]
+
+    def load_initial(self, chunk=2048):
+        """Leaves get the seeded primitive data; then conversion to conserved
+        variables, restriction of the parents and ghost fill, all on device."""
+        leaves = np.nonzero(self.wl.leaf_mask())[0]
+        inter = self.interior_view()
+        with torch.cuda.stream(self.stream):
+            for s in range(0, len(leaves), chunk):
+                idx = leaves[s:s + chunk]
+                prim = torch.from_numpy(self.wl.primitive_blocks(idx)).to(self.device,
+                                                                         non_blocking=False)
+                slots = torch.from_numpy(self.slot_of_key[idx].astype(np.int64)).to(self.device)
+                inter[slots] = prim.to(self.dtype)
+        self.stream.synchronize()
+        N.map_prim_to_cons(self.ctx, self.U, self.sp)
+        N.map_restrict(self.ctx, self.U, self.sp)
+        N.map_fill_ghosts(self.ctx, self.U, self.sp)
+        self.stream.synchronize()
+
+    def state_by_key(self, blocks=None) -> np.ndarray:
+        """FP64 copy of the state in the caller's key order (optionally a subset)."""
+        self.stream.synchronize()
+        if blocks is None:
+            slots = self.slot_of_key
+        else:
+            slots = self.slot_of_key[np.asarray(blocks)]
+        idx = torch.from_numpy(slots.astype(np.int64)).to(self.device)
+        return self.U.index_select(0, idx).to(torch.float64).cpu().numpy()
+
+    # ---------------------------------------------------------------- stages
+    def fill(self):
+        N.map_fill_ghosts(self.ctx, self.U, self.sp)
+
+    def restrict(self):
+        N.map_restrict(self.ctx, self.U, self.sp)
+
+    def cfl(self):
+        N.map_cfl_dt(self.ctx, self.U, self.dt, self.sp)
+        return self.dt
+
+    def step(self, Uout=None):
+        N.map_step(self.ctx, self.U, self.U if Uout is None else Uout, self.dt, self.sp)
+
+    def reflux(self):
+        N.map_reflux(self.ctx, self.U, self.dt, self.sp)
+
+    def totals(self) -> np.ndarray:
+        out = torch.zeros((len(self.wl.sims), NV), dtype=torch.float64, device=self.device)
+        N.map_totals(self.ctx, self.U, out, self.sp)
+        self.stream.synchronize()
+        return out.cpu().numpy()
+
+    def advance(self, nsteps):
+        N.map_advance(self.ctx, self.U, self.dt, nsteps, self.sp)
+
+    def graph_run(self, nsteps):
+        N.map_graph_run(self.ctx, self.U, self.dt, nsteps, self.sp)
+
+    def flags(self):
+        return N.map_status_flags(self.ctx, self.sp)
+
+    def set_launch(self, mode, grid_step=0, grid_fill=0):
+        N.map_set_launch(self.ctx, mode, grid_step, grid_fill)
+
+    def autotune(self):
+        return N.map_autotune(self.ctx, self.U, self.sp)
+
+    def sync(self):
+        self.stream.synchronize()

@@ -78,27 +78,43 @@ class Workload:
 
     # ------------------------------------------------------------ initial data
     def primitive_blocks(self, blocks) -> np.ndarray:
-        """Primitive interior values [len(blocks), 9, nz, ny, nx] (nz = 1 in 2-D)."""
+        """Primitive interior values [len(blocks), 9, nz, ny, nx] (nz = 1 in 2-D),
+        evaluated group by group (same sim and level) with array broadcasting."""
         blocks = np.asarray(blocks, dtype=np.int64)
         n = self.n
         nz = n if self.ndim == 3 else 1
-        out = np.zeros((len(blocks), NVAR, nz, n, n))
-        for i, b in enumerate(blocks):
-            sim, lv, ix, iy, iz = (int(v) for v in self.keys[b])
+        out = np.empty((len(blocks), NVAR, nz, n, n))
+        if len(blocks) == 0:
+            return out
+        kb = self.keys[blocks]
+        groups = {}
+        for i, (sim, lv) in enumerate(zip(kb[:, 0].tolist(), kb[:, 1].tolist())):
+            groups.setdefault((sim, lv), []).append(i)
+        ar = np.arange(n)
+        for (sim, lv), rows in groups.items():
+            rows = np.asarray(rows)
+            k = kb[rows]
             s = self.sims[sim]
             dx = self.dx(sim, lv)
-            gi = [ix * n + np.arange(n), iy * n + np.arange(n), iz * n + np.arange(nz)]
-            xc = s.lo[0] + (gi[0] + 0.5) * dx[0]
-            yc = s.lo[1] + (gi[1] + 0.5) * dx[1]
-            zc = s.lo[2] + (gi[2] + 0.5) * dx[2] if self.ndim == 3 else np.zeros(1)
-            Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
-            GZ, GY, GX = np.meshgrid(gi[2], gi[1], gi[0], indexing="ij")
-            nx_l = self.cells_at_level(sim, 0, lv)
-            ny_l = self.cells_at_level(sim, 1, lv)
-            gidx = (GZ.astype(np.uint64) * np.uint64(ny_l) + GY.astype(np.uint64)) * np.uint64(nx_l) \
-                + GX.astype(np.uint64)
-            w = self.ic(self, sim, lv, X, Y, Z, gidx)
-            out[i] = np.stack([np.broadcast_to(np.asarray(c, dtype=np.float64), X.shape) for c in w])
+            gx = (k[:, 2, None] * n + ar)[:, None, None, :]
+            gy = (k[:, 3, None] * n + ar)[:, None, :, None]
+            if self.ndim == 3:
+                gz = (k[:, 4, None] * n + ar)[:, :, None, None]
+                Z = s.lo[2] + (gz + 0.5) * dx[2]
+            else:
+                gz = np.zeros((len(rows), 1, 1, 1), dtype=np.int64)
+                Z = np.zeros((len(rows), 1, 1, 1))
+            X = s.lo[0] + (gx + 0.5) * dx[0]
+            Y = s.lo[1] + (gy + 0.5) * dx[1]
+            shape = (len(rows), nz, n, n)
+            nx_l = np.uint64(self.cells_at_level(sim, 0, lv))
+            ny_l = np.uint64(self.cells_at_level(sim, 1, lv))
+            gidx = (gz.astype(np.uint64) * ny_l + gy.astype(np.uint64)) * nx_l + gx.astype(np.uint64)
+            gidx = np.broadcast_to(gidx, shape)
+            w = self.ic(self, sim, lv, np.broadcast_to(X, shape), np.broadcast_to(Y, shape),
+                        np.broadcast_to(Z, shape), gidx)
+            for c, val in enumerate(w):
+                out[rows, c] = np.broadcast_to(np.asarray(val, dtype=np.float64), shape)
         return out
 
 

@@ -1,0 +1,164 @@
+"""Host-side tests of libmap.so (no GPU): exported symbols, block-tree
+validation errors, Morton slot order and the neighbour tables against a
+brute-force geometric search."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1204_5849_amd import native as N
+from paper_1204_5849_amd import workloads as W
+from tests.helpers import random_tree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(N.LIB_PATH):
+        from paper_1204_5849_amd import build
+        build.build()
+    return N.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    hdr = open(os.path.join(ROOT, "include", "map.h")).read()
+    names = set(re.findall(r"^\s*(?:map_status|const char\s*\*|void)\s*(map_\w+)\s*\(", hdr, re.M))
+    assert {"map_init_blocks", "map_step", "map_fill_ghosts", "map_cfl_dt", "map_restrict",
+            "map_prolong", "map_last_error", "map_destroy"} <= names
+    for n in names:
+        assert hasattr(L, n), n
+    assert names == set(N.EXPORTS)
+
+
+def _status(params, sims, keys):
+    ctx = N.C.c_void_p()
+    st = N.lib().map_init_blocks(N.C.byref(ctx), N.C.byref(params), len(sims), N.make_sims(sims),
+                                 len(keys), N.make_keys(keys))
+    if st == N.MAP_OK:
+        N.map_destroy(ctx)
+    return st
+
+
+def _sims2d(nb=(2, 2, 1), bc="periodic"):
+    return [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb, bc=((bc, bc),) * 3)]
+
+
+def test_tree_errors():
+    p = N.make_params(2)
+    sims = _sims2d()
+    base = W.base_keys(0, (2, 2, 1), 2)
+    assert _status(p, sims, base) == N.MAP_OK
+    assert _status(p, sims, np.concatenate([base, base[:1]])) == N.MAP_ETREE      # duplicate
+    assert _status(p, sims, base[1:]) == N.MAP_ETREE                              # base incomplete
+    kids = W.children_of(base[:1], 2)
+    assert _status(p, sims, np.concatenate([base, kids])) == N.MAP_OK
+    assert _status(p, sims, np.concatenate([base, kids[:3]])) == N.MAP_ETREE      # siblings
+    orphan = np.array([[0, 3, 0, 0, 0]], dtype=np.int32)
+    assert _status(p, sims, np.concatenate([base, orphan])) == N.MAP_ETREE        # no parent
+    bad = np.array([[0, 1, 5, 0, 0]], dtype=np.int32)
+    assert _status(p, sims, np.concatenate([base, bad])) == N.MAP_ETREE           # out of range
+    # 2:1 violation: level 3 next to a level-1 leaf
+    sims4 = _sims2d((4, 4, 1))
+    b4 = W.base_keys(0, (4, 4, 1), 2)
+    l2 = W.children_of(b4[:1], 2)
+    l3 = W.children_of(l2[3:4], 2)  # refine the child touching (1,1) corner
+    assert _status(p, sims4, np.concatenate([b4, l2, l3])) == N.MAP_ETREE
+    l2b = W.children_of(b4[[0, 1, 4, 5]], 2)
+    assert _status(p, sims4, np.concatenate([b4, l2b, l3])) == N.MAP_OK
+
+
+def test_param_errors():
+    sims = _sims2d()
+    base = W.base_keys(0, (2, 2, 1), 2)
+    assert _status(N.make_params(4), sims, base) == N.MAP_EINVAL
+    assert _status(N.make_params(2, limiter=7), sims, base) == N.MAP_EINVAL
+    assert _status(N.make_params(2, gamma=1.0), sims, base) == N.MAP_EINVAL
+    sims3 = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=(2, 2, 2), bc=(("periodic",) * 2,) * 3)]
+    assert _status(N.make_params(3, scheme="mmc"), sims3, W.base_keys(0, (2, 2, 2), 3)) == N.MAP_EINVAL
+    mixed = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=(2, 2, 1),
+                       bc=(("periodic", "outflow"),) * 3)]
+    assert _status(N.make_params(2), mixed, base) == N.MAP_EINVAL
+
+
+def test_call_order_and_workspace_errors():
+    w = W.orszag_tang(2)
+    ctx = N.map_init_blocks(N.make_params(2), w.sims, w.keys)
+    sz, _ = N.map_query(ctx)
+    L = N.lib()
+    assert L.map_step(ctx, 256, 256, 256, None) == N.MAP_ESTATE
+    assert L.map_fill_ghosts(ctx, 256, None) == N.MAP_ESTATE
+    assert L.map_bind_workspace(ctx, None, 10 ** 9, None) == N.MAP_EINVAL
+    assert L.map_bind_workspace(ctx, 256, sz.workspace_bytes - 1, None) == N.MAP_ENOMEM
+    assert b"need" in L.map_last_error()
+    N.map_destroy(ctx)
+
+
+def _morton(x, y, z):
+    out = 0
+    for b in range(21):
+        out |= ((x >> b) & 1) << (3 * b) | ((y >> b) & 1) << (3 * b + 1) | ((z >> b) & 1) << (3 * b + 2)
+    return out
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_morton_slot_order(ndim):
+    rng = np.random.default_rng(ndim)
+    nb = (3, 2, 1) if ndim == 2 else (2, 2, 2)
+    sims = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb, bc=(("periodic",) * 2,) * 3)] * 2
+    keys = random_tree(sims, ndim, 3, 0.3, rng)
+    p = N.make_params(ndim)
+    ctx = N.map_init_blocks(p, sims, keys)
+    sz, slot = N.map_query(ctx)
+    lmax = int(keys[:, 1].max())
+    order = sorted(range(len(keys)), key=lambda i: (keys[i, 0], _morton(
+        int(keys[i, 2]) << (lmax - keys[i, 1]), int(keys[i, 3]) << (lmax - keys[i, 1]),
+        int(keys[i, 4]) << (lmax - keys[i, 1])), keys[i, 1]))
+    assert [int(slot[i]) for i in order] == list(range(len(keys)))
+    index = {tuple(k): i for i, k in enumerate(keys.tolist())}
+    for i, (s, lv, x, y, z) in enumerate(keys.tolist()):
+        if lv > 1:
+            assert slot[index[(s, lv - 1, x >> 1, y >> 1, z >> 1)]] < slot[i]
+    assert sz.nleaves == int(W.leaf_mask(keys).sum())
+    N.map_destroy(ctx)
+
+
+@pytest.mark.parametrize("ndim,bc", [(2, "periodic"), (2, "outflow"), (3, "periodic"), (3, "mixed")])
+def test_neighbours_match_brute_force(ndim, bc):
+    rng = np.random.default_rng(11 + ndim)
+    nb = (3, 4, 1) if ndim == 2 else (2, 3, 2)
+    if bc == "mixed":
+        bcs = (("periodic", "periodic"), ("outflow", "outflow"), ("periodic", "periodic"))
+    else:
+        bcs = ((bc, bc),) * 3
+    sims = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb, bc=bcs)]
+    keys = random_tree(sims, ndim, 3, 0.35, rng)
+    ctx = N.map_init_blocks(N.make_params(ndim), sims, keys)
+    got = N.map_neighbors(ctx, len(keys))
+    N.map_destroy(ctx)
+    n = 16
+    index = {tuple(k): i for i, k in enumerate(keys.tolist())}
+    for i, (s, lv, kx, ky, kz) in enumerate(keys.tolist()):
+        kc = (kx, ky, kz)
+        for dz in ((-1, 0, 1) if ndim == 3 else (0,)):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    di = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)
+                    if (dx, dy, dz) == (0, 0, 0):
+                        assert got[i, di] == -2
+                        continue
+                    # one ghost cell of that direction, mapped through the boundary
+                    src = []
+                    for d, dd in enumerate((dx, dy, dz)):
+                        if d >= ndim:
+                            src.append(0)
+                            continue
+                        loc = -1 if dd < 0 else (n if dd > 0 else 0)
+                        G = kc[d] * n + loc
+                        Nl = nb[d] * n << (lv - 1)
+                        if G < 0 or G >= Nl:
+                            G = G % Nl if bcs[d][0] == "periodic" else min(max(G, 0), Nl - 1)
+                        src.append(G // n)
+                    want = index.get((s, lv, *src), -1)
+                    assert got[i, di] == want, (i, (dx, dy, dz))

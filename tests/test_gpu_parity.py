@@ -1,0 +1,255 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar (FP64): relative L-infinity per variable, max|gpu - oracle| / max|oracle|,
+<= 1e-11 after N steps; stages whose arithmetic is a copy or a fixed-order
+average (ghost fill, prolongation, restriction, the initial conversion) must
+match bit for bit.  FP32 results are compared in relative L1 (stated per test).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1204_5849_amd import native as N  # noqa: E402
+from paper_1204_5849_amd import workloads as W  # noqa: E402
+from tests.helpers import random_tree, rel_linf  # noqa: E402
+
+TOL64 = 1e-11
+
+
+def _say(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    N.lib()  # fails loudly if libmap.so is missing
+    return "cuda:0"
+
+
+def _sim(w, **kw):
+    from paper_1204_5849_amd.sim import Simulation
+    s = Simulation(w, **kw)
+    s.load_initial()
+    return s
+
+
+def _leaf_interiors(w, U):
+    leaves = w.leaf_mask()
+    if w.ndim == 3:
+        return U[leaves][:, :, 2:-2, 2:-2, 2:-2]
+    return U[leaves][:, :, :, 2:-2, 2:-2]
+
+
+def _check(w, gpu, ora, tol, what):
+    err = rel_linf(_leaf_interiors(w, gpu), _leaf_interiors(w, ora))
+    _say(f"{what}: rel Linf per var {np.array2string(err, precision=2)}")
+    assert np.all(err <= tol), (what, err)
+
+
+def test_init_fill_bitwise_ot(dev, orc):
+    _say("orszag_tang 128^2 init + fill")
+    w = W.orszag_tang(8)
+    s = _sim(w)
+    A = orc.load_workload(w)
+    assert np.array_equal(s.state_by_key(), A.state)
+
+
+def _tree(ndim, seed, bc="periodic", levels=3):
+    rng = np.random.default_rng(seed)
+    nb = (3, 2, 1) if ndim == 2 else (2, 2, 2)
+    if bc == "mixed":
+        bcs = (("periodic", "periodic"), ("outflow", "outflow"), ("periodic", "periodic"))
+    else:
+        bcs = ((bc, bc),) * 3
+    sims = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb, bc=bcs)]
+    return sims, random_tree(sims, ndim, levels, 0.35, rng)
+
+
+def _tree_ic(wl, sim, lv, x, y, z, g):
+    tp = 2 * np.pi
+    return [1.0 + 0.3 * np.sin(tp * x) * np.cos(tp * y), 0.4 * np.sin(tp * y),
+            0.3 * np.sin(tp * (x + z)), 0.1 * np.cos(tp * z), 0.5 + 0.2 * np.cos(tp * y),
+            0.3 * np.sin(tp * x), 0.2 + 0.1 * np.sin(tp * z), 1.0 + 0.2 * np.cos(tp * x),
+            0.05 * np.sin(tp * y)]
+
+
+@pytest.mark.parametrize("ndim,bc", [(2, "periodic"), (2, "outflow"), (3, "periodic"), (3, "mixed")])
+def test_init_fill_bitwise_amr(dev, orc, ndim, bc):
+    """Restriction, same-level copies, outflow clamping and prolongated ghosts."""
+    _say(f"amr tree init+fill ndim={ndim} bc={bc}")
+    sims, keys = _tree(ndim, 31 + ndim, bc)
+    w = W.Workload(name="tree", ndim=ndim, sims=sims, keys=keys, ic=_tree_ic)
+    s = _sim(w)
+    A = orc.load_workload(w)
+    assert (keys[:, 1] == 3).any()
+    assert np.array_equal(s.state_by_key(), A.state)
+
+
+def test_cfl_record_matches(dev, orc):
+    _say("cfl record orszag_tang")
+    w = W.orszag_tang(8)
+    s = _sim(w)
+    A = orc.load_workload(w)
+    rec = s.cfl().cpu().numpy()[0]
+    r = A.cfl()[0]
+    np.testing.assert_allclose(rec, [r.dt, r.ch, r.damp, r.alpha], rtol=1e-14)
+
+
+def _run_both(w, nsteps, **kw):
+    import oracle as orc
+    s = _sim(w, **kw)
+    A = orc.load_workload(w)
+    tr = A.run(nsteps, trace=True)
+    dts = []
+    for _ in range(nsteps):
+        s.advance(1)
+        dts.append(s.dt.cpu().numpy().copy())
+    return s, A, tr, np.array(dts)
+
+
+@pytest.mark.parametrize("nsteps", [1, 100])
+def test_orszag_tang_lf_fp64(dev, nsteps):
+    """Configuration 1: OT 128^2, 8x8 blocks, LF + minmod, FP64, 100 steps."""
+    _say(f"orszag_tang LF fp64 {nsteps} steps")
+    w = W.orszag_tang(8)
+    s, A, tr, dts = _run_both(w, nsteps)
+    np.testing.assert_allclose(dts[:, 0, 0], tr[:, 0, 0], rtol=1e-11)
+    _check(w, s.state_by_key(), A.state, TOL64 if nsteps > 1 else 1e-13, f"OT {nsteps} steps")
+
+
+@pytest.mark.parametrize("ndim,scheme,limiter,bc", [
+    (2, "lf", "minmod", "periodic"), (2, "mmc", "vanleer", "periodic"), (2, "lf", "vanleer", "outflow"),
+    (2, "mmc", "minmod", "outflow"), (3, "lf", "minmod", "periodic"), (3, "lf", "minmod", "mixed")])
+def test_amr_tree_steps_fp64(dev, ndim, scheme, limiter, bc):
+    """Random 2:1 trees: step, reflux, restriction and fill over 8 cycles."""
+    _say(f"amr tree steps ndim={ndim} {scheme}/{limiter} bc={bc}")
+    sims, keys = _tree(ndim, 7 + ndim + len(bc), bc)
+    w = W.Workload(name="tree", ndim=ndim, sims=sims, keys=keys, ic=_tree_ic, scheme=scheme,
+                   limiter=limiter)
+    s, A, tr, dts = _run_both(w, 8)
+    np.testing.assert_allclose(dts[:, 0, 0], tr[:, 0, 0], rtol=1e-12)
+    _check(w, s.state_by_key(), A.state, TOL64, "tree 8 cycles")
+    # parents hold the restriction of the final leaves, ghosts the final fill
+    assert np.allclose(s.state_by_key(), A.state, rtol=0, atol=1e-11 * np.abs(A.state).max())
+
+
+def test_amr_resistive_3d_fp64(dev):
+    _say("harris 3d small, eta, fastspeed GLM, 4 steps")
+    w = W.harris3d(nbase=2, levels=3, precision="fp64")
+    s, A, tr, dts = _run_both(w, 4)
+    np.testing.assert_allclose(dts[:, 0], tr[:, 0], rtol=1e-12)
+    _check(w, s.state_by_key(), A.state, TOL64, "harris small 4 steps")
+
+
+def test_blast3d_small_fp64(dev):
+    _say("blast 3d small fp64 5 steps")
+    w = W.blast3d(nbase=2, levels=2, precision="fp64")
+    s, A, tr, dts = _run_both(w, 5)
+    _check(w, s.state_by_key(), A.state, TOL64, "blast small 5 steps")
+
+
+def test_kh_ensemble_small_fp64(dev):
+    """Uneven simulations in one launch: per-simulation dt and fill."""
+    _say("kh ensemble 5 sims fp64 10 steps")
+    w = W.kh_ensemble(nsims=5, kmin=2, kmax=5, precision="fp64")
+    s, A, tr, dts = _run_both(w, 10)
+    np.testing.assert_allclose(dts[:, :, 0], tr[:, :, 0], rtol=1e-12)
+    _check(w, s.state_by_key(), A.state, TOL64, "kh 10 steps")
+
+
+def test_ot_amr_config_mmc_fp64(dev):
+    """Configuration 2 block list (3840 blocks, MMC + van Leer), 3 cycles."""
+    import os
+    _say("ot amr 3840 blocks mmc 3 steps")
+    path = os.path.join(os.path.dirname(__file__), "golden", "ot_amr_grid.txt")
+    keys = np.loadtxt(path, dtype=np.int32, comments="#")
+    w = W.ot_amr(keys)
+    s, A, tr, dts = _run_both(w, 3)
+    _check(w, s.state_by_key(), A.state, TOL64, "ot amr 3 steps")
+
+
+def test_totals_match(dev, orc):
+    _say("totals kh small")
+    w = W.kh_ensemble(nsims=3, kmin=2, kmax=4, precision="fp64")
+    s = _sim(w)
+    A = orc.load_workload(w)
+    np.testing.assert_allclose(s.totals(), A.totals(), rtol=1e-13, atol=1e-15)
+
+
+def test_graph_equals_eager_and_per_block_equals_batched(dev):
+    _say("graph vs eager vs per-block")
+    sims, keys = _tree(2, 5, "outflow")
+    w = W.Workload(name="tree", ndim=2, sims=sims, keys=keys, ic=_tree_ic)
+    a = _sim(w)
+    b = _sim(w)
+    c = _sim(w, launch="per_block")
+    a.advance(5)
+    b.graph_run(5)
+    c.advance(5)
+    ua, ub, uc = a.state_by_key(), b.state_by_key(), c.state_by_key()
+    assert np.array_equal(ua, ub)
+    assert np.array_equal(ua, uc)
+    a.advance(3)
+    a2 = a.state_by_key()
+    b.graph_run(3)  # replays of the captured cycle keep matching
+    assert np.array_equal(a2, b.state_by_key())
+
+
+def test_determinism_3d(dev):
+    _say("determinism blast small fp32")
+    w = W.blast3d(nbase=2, levels=2, precision="fp32")
+    a = _sim(w)
+    b = _sim(w)
+    a.graph_run(4)
+    b.graph_run(4)
+    assert np.array_equal(a.state_by_key(), b.state_by_key())
+
+
+@pytest.mark.parametrize("name", ["ot", "blast"])
+def test_fp32_mixed_l1_vs_fp64_oracle(dev, name):
+    """FP32 state with FP64 pressure recovery and CFL against the FP64 oracle:
+    relative L1 of rho, e and |B| <= 1e-4 (OT 100 steps, blast 10 steps)."""
+    import oracle as orc
+    if name == "ot":
+        w, n = W.orszag_tang(8, precision="fp32"), 100
+    else:
+        w, n = W.blast3d(nbase=2, levels=2, precision="fp32"), 10
+    _say(f"fp32 vs fp64 oracle {name} {n} steps")
+    s = _sim(w)
+    A = orc.load_workload(w)
+    s.advance(n)
+    A.run(n)
+    g = _leaf_interiors(w, s.state_by_key())
+    o = _leaf_interiors(w, A.state)
+    for k, nm in ((0, "rho"), (7, "e")):
+        e = np.abs(g[:, k] - o[:, k]).mean() / np.abs(o[:, k]).mean()
+        _say(f"  {nm} rel L1 {e:.2e}")
+        assert e <= 1e-4
+    bg = np.sqrt((g[:, 4:7] ** 2).sum(axis=1))
+    bo = np.sqrt((o[:, 4:7] ** 2).sum(axis=1))
+    e = np.abs(bg - bo).mean() / np.abs(bo).mean()
+    _say(f"  |B| rel L1 {e:.2e}")
+    assert e <= 1e-4
+
+
+def test_status_flags(dev):
+    _say("status flags")
+    w = W.orszag_tang(2)
+    s = _sim(w)
+    s.advance(2)
+    st, cnt = s.flags()
+    assert st == N.MAP_OK and cnt[2] == 0 and cnt[3] == 0
+    slot = int(s.slot_of_key[0])
+    s.U[slot, 7, 0, 5, 5] = 0.0  # e = 0 -> negative pressure, forced from the host
+    s.cfl()
+    st, cnt = s.flags()
+    assert st == N.MAP_ENEGPRESSURE and cnt[2] >= 1
+    s.U[slot, 0, 0, 6, 6] = float("nan")
+    s.cfl()
+    st, cnt = s.flags()
+    assert st == N.MAP_ENONFINITE and cnt[3] >= 1
