@@ -3,7 +3,10 @@
 Bar (FP64): relative L-infinity per variable, max|gpu - oracle| / max|oracle|,
 <= 1e-11 after N steps; stages whose arithmetic is a copy or a fixed-order
 average (ghost fill, prolongation, restriction, the initial conversion) must
-match bit for bit.  FP32 results are compared in relative L1 (stated per test).
+match bit for bit.  psi is measured against its natural scale c_h max|B| (the
+GLM pair psi +- c_h B_n travels together), because in divergence-free
+problems psi itself is a cancellation residue many orders below that scale.
+FP32 results are compared in relative L1 (stated per test).
 """
 import numpy as np
 import pytest
@@ -45,8 +48,12 @@ def _leaf_interiors(w, U):
     return U[leaves][:, :, :, 2:-2, 2:-2]
 
 
-def _check(w, gpu, ora, tol, what):
-    err = rel_linf(_leaf_interiors(w, gpu), _leaf_interiors(w, ora))
+def _check(w, gpu, ora, tol, what, ch=None):
+    g, o = _leaf_interiors(w, gpu), _leaf_interiors(w, ora)
+    err = rel_linf(g, o)
+    if ch is not None:
+        scale = max(np.abs(o[:, 8]).max(), float(np.max(ch)) * np.abs(o[:, 4:7]).max())
+        err[8] = np.abs(g[:, 8] - o[:, 8]).max() / scale
     _say(f"{what}: rel Linf per var {np.array2string(err, precision=2)}")
     assert np.all(err <= tol), (what, err)
 
@@ -95,7 +102,9 @@ def test_cfl_record_matches(dev, orc):
     w = W.orszag_tang(8)
     s = _sim(w)
     A = orc.load_workload(w)
-    rec = s.cfl().cpu().numpy()[0]
+    s.cfl()
+    s.sync()
+    rec = s.dt.cpu().numpy()[0]
     r = A.cfl()[0]
     np.testing.assert_allclose(rec, [r.dt, r.ch, r.damp, r.alpha], rtol=1e-14)
 
@@ -108,6 +117,7 @@ def _run_both(w, nsteps, **kw):
     dts = []
     for _ in range(nsteps):
         s.advance(1)
+        s.sync()  # the dt record is written on the simulation's stream
         dts.append(s.dt.cpu().numpy().copy())
     return s, A, tr, np.array(dts)
 
@@ -119,7 +129,8 @@ def test_orszag_tang_lf_fp64(dev, nsteps):
     w = W.orszag_tang(8)
     s, A, tr, dts = _run_both(w, nsteps)
     np.testing.assert_allclose(dts[:, 0, 0], tr[:, 0, 0], rtol=1e-11)
-    _check(w, s.state_by_key(), A.state, TOL64 if nsteps > 1 else 1e-13, f"OT {nsteps} steps")
+    _check(w, s.state_by_key(), A.state, TOL64 if nsteps > 1 else 1e-13, f"OT {nsteps} steps",
+           ch=tr[-1, :, 1])
 
 
 @pytest.mark.parametrize("ndim,scheme,limiter,bc", [
@@ -133,9 +144,11 @@ def test_amr_tree_steps_fp64(dev, ndim, scheme, limiter, bc):
                    limiter=limiter)
     s, A, tr, dts = _run_both(w, 8)
     np.testing.assert_allclose(dts[:, 0, 0], tr[:, 0, 0], rtol=1e-12)
-    _check(w, s.state_by_key(), A.state, TOL64, "tree 8 cycles")
+    _check(w, s.state_by_key(), A.state, TOL64, "tree 8 cycles", ch=tr[-1, :, 1])
     # parents hold the restriction of the final leaves, ghosts the final fill
-    assert np.allclose(s.state_by_key(), A.state, rtol=0, atol=1e-11 * np.abs(A.state).max())
+    full = s.state_by_key()
+    for k in range(8):
+        assert np.abs(full[:, k] - A.state[:, k]).max() <= TOL64 * np.abs(A.state[:, k]).max() + 1e-300
 
 
 def test_amr_resistive_3d_fp64(dev):
@@ -143,14 +156,14 @@ def test_amr_resistive_3d_fp64(dev):
     w = W.harris3d(nbase=2, levels=3, precision="fp64")
     s, A, tr, dts = _run_both(w, 4)
     np.testing.assert_allclose(dts[:, 0], tr[:, 0], rtol=1e-12)
-    _check(w, s.state_by_key(), A.state, TOL64, "harris small 4 steps")
+    _check(w, s.state_by_key(), A.state, TOL64, "harris small 4 steps", ch=tr[-1, :, 1])
 
 
 def test_blast3d_small_fp64(dev):
     _say("blast 3d small fp64 5 steps")
     w = W.blast3d(nbase=2, levels=2, precision="fp64")
     s, A, tr, dts = _run_both(w, 5)
-    _check(w, s.state_by_key(), A.state, TOL64, "blast small 5 steps")
+    _check(w, s.state_by_key(), A.state, TOL64, "blast small 5 steps", ch=tr[-1, :, 1])
 
 
 def test_kh_ensemble_small_fp64(dev):
@@ -159,7 +172,7 @@ def test_kh_ensemble_small_fp64(dev):
     w = W.kh_ensemble(nsims=5, kmin=2, kmax=5, precision="fp64")
     s, A, tr, dts = _run_both(w, 10)
     np.testing.assert_allclose(dts[:, :, 0], tr[:, :, 0], rtol=1e-12)
-    _check(w, s.state_by_key(), A.state, TOL64, "kh 10 steps")
+    _check(w, s.state_by_key(), A.state, TOL64, "kh 10 steps", ch=tr[-1, :, 1])
 
 
 def test_ot_amr_config_mmc_fp64(dev):
@@ -170,7 +183,7 @@ def test_ot_amr_config_mmc_fp64(dev):
     keys = np.loadtxt(path, dtype=np.int32, comments="#")
     w = W.ot_amr(keys)
     s, A, tr, dts = _run_both(w, 3)
-    _check(w, s.state_by_key(), A.state, TOL64, "ot amr 3 steps")
+    _check(w, s.state_by_key(), A.state, TOL64, "ot amr 3 steps", ch=tr[-1, :, 1])
 
 
 def test_totals_match(dev, orc):
