@@ -15,8 +15,8 @@
 //   * each face flux is evaluated once; the next plane is prefetched from
 //     HBM while the current one is processed; every HBM access is a
 //     contiguous row of the structure-of-arrays tile.
-// 2-D workgroups hold 12 blocks (240 columns), 3-D workgroups one block
-// (400 columns, 7 waves).  A persistent grid strides over the work list.
+// 2-D workgroups hold 14 blocks, 3-D workgroups one block (5 waves).  A
+// persistent grid strides over the work list.
 #include <type_traits>
 
 #include "kernels.hpp"
@@ -24,28 +24,50 @@
 
 namespace mapk {
 
+// Lane layout.  Only the columns whose face states feed a face compute: the
+// ring one cell outside the interior, minus its corners in 3-D (which no
+// face reads), i.e. 18 columns per 2-D block and 320 = 5 waves per 3-D block.
+// The remaining cells of the padded plane (outer ring, 3-D ring corners)
+// are only loaded, by the first threads, one plane ahead.
 template <int NDIM>
 struct SG;
 template <>
 struct SG<2> {
-    static constexpr int XS = PD, BPW = 12, NT = 256;
+    static constexpr int XS = PD, BPW = 14, NT = 256, NCOL = NB + 2, NX = 2;
 };
 template <>
 struct SG<3> {
-    static constexpr int XS = PD * PD, BPW = 1, NT = 448;
+    static constexpr int XS = PD * PD, BPW = 1, NT = 320, NCOL = 320, NX = 80;
 };
 
-template <int D, typename T, bool MIXED>
-__device__ __forceinline__ void rusanov(const Phys<T, MIXED> &ph, const T L[NV], const T R[NV],
-                                        T ch, T ch2, T f[NV])
+// Rusanov flux (Equ:LFFlux) with alpha = max of the two fast speeds for the
+// MHD components and c_h for the GLM pair (B_D, psi); the pressures of both
+// states are given (computed once when the states were formed)
+template <int D, typename T>
+__device__ __forceinline__ void rusanov_p(const T L[NV], T pL, const T R[NV], T pR, T gamma,
+                                          T ch, T ch2, T f[NV])
 {
+    Prim<T> wL, wR;
+    wL.ir = Num<T>::rcp(L[RHO]);
+    wL.vx = L[MX] * wL.ir;
+    wL.vy = L[MY] * wL.ir;
+    wL.vz = L[MZ] * wL.ir;
+    wL.bb = L[BX] * L[BX] + L[BY] * L[BY] + L[BZ] * L[BZ];
+    wL.p = pL;
+    wR.ir = Num<T>::rcp(R[RHO]);
+    wR.vx = R[MX] * wR.ir;
+    wR.vy = R[MY] * wR.ir;
+    wR.vz = R[MZ] * wR.ir;
+    wR.bb = R[BX] * R[BX] + R[BY] * R[BY] + R[BZ] * R[BZ];
+    wR.p = pR;
     T FL[NV], FR[NV];
-    T sL = ph.template flux<D, true>(L, ch2, FL);
-    T sR = ph.template flux<D, true>(R, ch2, FR);
-    T al = sL > sR ? sL : sR;
+    flux_w<D>(L, wL, ch2, FL);
+    flux_w<D>(R, wR, ch2, FR);
+    const T sL = speed_w<D>(L, wL, gamma), sR = speed_w<D>(R, wR, gamma);
+    const T al = sL > sR ? sL : sR;
 #pragma unroll
     for (int k = 0; k < NV; k++) {
-        T ak = (k == BX + D || k == PSI) ? ch : al;
+        const T ak = (k == BX + D || k == PSI) ? ch : al;
         f[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * ak * (R[k] - L[k]);
     }
 }
@@ -59,33 +81,91 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
     constexpr int SY = PD;  // in-plane y stride (3-D)
     __shared__ T su[BPW * NV * XS];
     __shared__ T srf[BPW * DIN * NV * XS];
+    __shared__ T spr[BPW * DIN * XS];
     __shared__ T sj[RESIST ? BPW * 5 * XS : 1];
 
+    // ---- this thread's column and its extra (load-only) cell
     const int t = threadIdx.x;
-    const int lb = t / XS;
-    const int q = t - lb * XS;
-    const bool lane = lb < BPW;
-    const int qx = q % PD - NG;
-    const int qy = NDIM == 3 ? q / PD - NG : 0;
-    const bool xE = qx >= -1 && qx <= NB, xI = qx >= 0 && qx < NB;
-    const bool yE = NDIM == 2 || (qy >= -1 && qy <= NB);
+    int lb, qx, qy;
+    bool lane;
+    if constexpr (NDIM == 3) {
+        lb = 0;
+        lane = t < SG<3>::NCOL;
+        if (t < NB) {
+            qx = t;
+            qy = -1;
+        } else if (t < NB + NB * (NB + 2)) {
+            const int r = t - NB;
+            qy = r / (NB + 2);
+            qx = r - qy * (NB + 2) - 1;
+        } else {
+            qx = t - NB - NB * (NB + 2);
+            qy = NB;
+        }
+    } else {
+        lb = t / SG<2>::NCOL;
+        lane = lb < BPW;
+        qx = t - lb * SG<2>::NCOL - 1;
+        qy = 0;
+    }
+    if (!lane) {
+        lb = 0;
+        qx = 0;
+        qy = 0;
+    }
+    const int q = (NDIM == 3 ? (qy + NG) * PD : 0) + qx + NG;
+    int xq = -1, xlb = 0;
+    if constexpr (NDIM == 3) {
+        if (t < SG<3>::NX) {
+            int ex, ey;
+            if (t < PD) {
+                ex = t - NG;
+                ey = -NG;
+            } else if (t < 2 * PD) {
+                ex = t - PD - NG;
+                ey = NB + 1;
+            } else if (t < 2 * PD + NB + 2) {
+                ex = -NG;
+                ey = t - 2 * PD - 1;
+            } else if (t < 2 * PD + 2 * (NB + 2)) {
+                ex = NB + 1;
+                ey = t - 2 * PD - (NB + 2) - 1;
+            } else {
+                const int c = t - 2 * PD - 2 * (NB + 2);
+                ex = (c & 1) ? NB : -1;
+                ey = (c & 2) ? NB : -1;
+            }
+            xq = (ey + NG) * PD + ex + NG;
+        }
+    } else {
+        if (t < SG<2>::NX * BPW) {
+            xlb = t >> 1;
+            xq = (t & 1) ? PD - 1 : 0;
+        }
+    }
+    const bool xI = qx >= 0 && qx < NB;
     const bool yI = NDIM == 2 || (qy >= 0 && qy < NB);
-    const bool inE = lane && xE && yE;
     const bool inI = lane && xI && yI;
 
     Phys<T, MIXED> ph;
     ph.gamma = (T)a.gamma;
     ph.gm1 = (T)(a.gamma - 1.0);
     ph.gm1d = a.gamma - 1.0;
+    const T gam = (T)a.gamma;
     const T *Uin = (const T *)a.Uin;
     T *Uout = (T *)a.Uout;
     T *fbuf = (T *)a.fbuf;
     const int lim = a.limiter;
 
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-        const int li = item * BPW + lb;
-        const bool has = lane && li < a.nleaves;
-        const int slot = has ? a.leaves[li] : 0;
+        // 3-D: one block per workgroup, so the block and everything derived
+        // from it are wave-uniform (scalar registers)
+        const int li = NDIM == 3 ? item : item * BPW + lb;
+        const bool has = NDIM == 3 ? (item < a.nleaves) : (lane && li < a.nleaves);
+        const int slot = NDIM == 3 ? a.leaves[item] : (has ? a.leaves[li] : 0);
+        const int lix = item * BPW + xlb;
+        const bool xhas = xq >= 0 && lix < a.nleaves;
+        const int xslot = xhas ? a.leaves[lix] : 0;
         const BlockRec br = a.blk[slot];
         const map_dt rec = a.dt[br.sim];
         const double *dxp = a.lvl_dx + ((size_t)br.sim * (MAXL + 1) + br.level) * 3;
@@ -100,6 +180,7 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         const T dt = (T)rec.dt, ch = (T)rec.ch, ch2 = (T)(rec.ch * rec.ch), damp = (T)rec.damp;
         const T eta = (T)a.eta;
         const T *ub = Uin + (size_t)slot * NV * P;
+        const T *xb = Uin + (size_t)xslot * NV * P;
         T *ob = Uout + (size_t)slot * NV * P;
 
         auto load = [&](T(&dst)[NV], int k) {
@@ -115,12 +196,21 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                 dst[EN] = T(4);
             }
         };
+        auto load_x = [&](T(&dst)[NV], int k) {
+            if (xhas) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    dst[v] = xb[(size_t)v * P + (k + NG) * XS + xq];
+            }
+        };
 
-        T um[NV], u0[NV], up[NV], upp[NV];
+        T um[NV], u0[NV], up[NV], upp[NV], xc[NV];
         load(um, -2);
         load(u0, -1);
         load(up, 0);
+        load_x(xc, -1);
         T Lm_prev[NV], fm_prev[NV], w_prev[NV], s_prev[4];
+        T pLm_prev = T(1);
         T rin_prev[4], jm1[3], jm2[3];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
@@ -140,21 +230,31 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         }
 
         for (int k = -1; k <= NB; ++k) {
-            if (k + 2 <= NB + 1)
-                load(upp, k + 2);
-            // ---- (A) publish plane k
+            const bool kI = k >= 0 && k < NB;
+            // ---- (A) publish plane k (own column and the load-only cell)
             if (lane) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     su[(lb * NV + v) * XS + q] = u0[v];
             }
+            if (xhas) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    su[(xlb * NV + v) * XS + xq] = xc[v];
+            }
+            if (k + 2 <= NB + 1)
+                load(upp, k + 2);
+            if (k + 1 <= NB + 1)
+                load_x(xc, k + 1);
             __syncthreads();
 
-            T Lin[DIN][NV], Lm[NV], Rm[NV];
+            T Lin[DIN][NV], pLin[DIN], Lm[NV], Rm[NV];
+            T pLm = T(1), pRm = T(1);
             T src[4] = {T(0), T(0), T(0), T(0)};
             T jc[3] = {T(0), T(0), T(0)};
-            const bool kI = k >= 0 && k < NB;
-            if (inE) {
+            // planes -1 and NB only feed the faces between planes: interior columns
+            const bool work = lane && (kI || inI);
+            if (work) {
                 // slopes from the old-time differences (limiter1)
                 T dl[NDIM][NV];
 #pragma unroll
@@ -165,50 +265,50 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                         dl[1][v] = limiter(lim, u0[v] - row[q - SY], row[q + SY] - u0[v]);
                     dl[MD][v] = limiter(lim, u0[v] - um[v], up[v] - u0[v]);
                 }
+                // half-step predictor u~ = u - dt/(2dx) sum_d [f(u + D/2) - f(u - D/2)],
+                // evaluated optimistically; if any face state of the cell has
+                // rho <= 0 or p <= 0 the slopes fall back to zero and u~ = u
+                T acc[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    acc[v] = T(0);
                 bool ok = true;
+                auto pred = [&](auto dc) {
+                    constexpr int d = decltype(dc)::value;
+                    T s1[NV], f1[NV], f2[NV];
+                    Prim<T> w;
 #pragma unroll
-                for (int d = 0; d < NDIM; d++) {
-                    T s1[NV], s2[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; v++) {
+                    for (int v = 0; v < NV; v++)
                         s1[v] = u0[v] + T(0.5) * dl[d][v];
-                        s2[v] = u0[v] - T(0.5) * dl[d][v];
-                    }
-                    bool a1 = ph.admissible(s1), a2 = ph.admissible(s2);
-                    ok = ok && a1 && a2;
-                }
+                    prim_of(ph, s1, w);
+                    ok = ok && admissible_w(s1, w);
+                    flux_w<d>(s1, w, ch2, f1);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        s1[v] = u0[v] - T(0.5) * dl[d][v];
+                    prim_of(ph, s1, w);
+                    ok = ok && admissible_w(s1, w);
+                    flux_w<d>(s1, w, ch2, f2);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        acc[v] += hdt[d] * (f1[v] - f2[v]);
+                };
+                pred(std::integral_constant<int, 0>{});
+                pred(std::integral_constant<int, 1>{});
+                if constexpr (NDIM == 3)
+                    pred(std::integral_constant<int, 2>{});
                 if (!ok) {
 #pragma unroll
                     for (int d = 0; d < NDIM; d++)
 #pragma unroll
                         for (int v = 0; v < NV; v++)
                             dl[d][v] = T(0);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        acc[v] = T(0);
                     if (has)
                         atomicAdd(&a.cnt[0], 1ull);
                 }
-                // half-step predictor: u~ = u - dt/(2dx) sum_d [f(u + D/2) - f(u - D/2)]
-                T acc[NV];
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    acc[v] = T(0);
-                auto pred = [&](auto dc) {
-                    constexpr int d = decltype(dc)::value;
-                    T sp[NV], sm[NV], fp[NV], fm[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; v++) {
-                        sp[v] = u0[v] + T(0.5) * dl[d][v];
-                        sm[v] = u0[v] - T(0.5) * dl[d][v];
-                    }
-                    ph.template flux<d, false>(sp, ch2, fp);
-                    ph.template flux<d, false>(sm, ch2, fm);
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        acc[v] += hdt[d] * (fp[v] - fm[v]);
-                };
-                pred(std::integral_constant<int, 0>{});
-                pred(std::integral_constant<int, 1>{});
-                if constexpr (NDIM == 3)
-                    pred(std::integral_constant<int, 2>{});
                 T ut[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
@@ -219,27 +319,32 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
 #pragma unroll
                 for (int d = 0; d < NDIM; d++) {
                     T L[NV], R[NV];
+                    Prim<T> wl, wr;
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
                         L[v] = ut[v] + T(0.5) * dl[d][v];
                         R[v] = ut[v] - T(0.5) * dl[d][v];
                     }
+                    prim_of(ph, L, wl);
+                    prim_of(ph, R, wr);
                     bool others = true;
 #pragma unroll
                     for (int e = 0; e < NDIM; e++)
                         if (e != d)
                             others = others && qc[e] >= 0 && qc[e] < NB;
-                    if (!ph.admissible(L)) {
+                    if (!admissible_w(L, wl)) {
 #pragma unroll
                         for (int v = 0; v < NV; v++)
                             L[v] = ut[v];
+                        prim_of(ph, L, wl);
                         if (has && others && qc[d] < NB)
                             atomicAdd(&a.cnt[1], 1ull);
                     }
-                    if (!ph.admissible(R)) {
+                    if (!admissible_w(R, wr)) {
 #pragma unroll
                         for (int v = 0; v < NV; v++)
                             R[v] = ut[v];
+                        prim_of(ph, R, wr);
                         if (has && others && qc[d] >= 0)
                             atomicAdd(&a.cnt[1], 1ull);
                     }
@@ -249,12 +354,16 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                             srf[((lb * DIN + d) * NV + v) * XS + q] = R[v];
                             Lin[d < DIN ? d : 0][v] = L[v];
                         }
+                        spr[(lb * DIN + d) * XS + q] = wr.p;
+                        pLin[d < DIN ? d : 0] = wl.p;
                     } else {
 #pragma unroll
                         for (int v = 0; v < NV; v++) {
                             Lm[v] = L[v];
                             Rm[v] = R[v];
                         }
+                        pLm = wl.p;
+                        pRm = wr.p;
                     }
                 }
                 // EGLM sources from central differences of u^n
@@ -319,7 +428,7 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                     }
                 }
             }
-            __syncthreads();  // (B) right face states and eta J published
+            __syncthreads();  // (B) right face states, their pressures and eta J published
 
             // ---- fluxes of the in-plane faces of plane k and of the face k-1/2
             T fin[DIN][NV];
@@ -333,7 +442,8 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     R[v] = srf[((lb * DIN + 0) * NV + v) * XS + q + 1];
-                rusanov<0>(ph, Lin[0], R, ch, ch2, fin[0]);
+                rusanov_p<0>(Lin[0], pLin[0], R, spr[(lb * DIN + 0) * XS + q + 1], gam, ch, ch2,
+                             fin[0]);
             }
             if constexpr (NDIM == 3) {
                 if (dof[1]) {
@@ -341,7 +451,8 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         R[v] = srf[((lb * DIN + 1) * NV + v) * XS + q + SY];
-                    rusanov<1>(ph, Lin[1], R, ch, ch2, fin[1]);
+                    rusanov_p<1>(Lin[1], pLin[1], R, spr[(lb * DIN + 1) * XS + q + SY], gam, ch,
+                                 ch2, fin[1]);
                 }
             }
             if constexpr (RESIST) {
@@ -363,7 +474,7 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
             const bool dom = inI && k >= 0;
             T fmc[NV];
             if (dom)
-                rusanov<MD>(ph, Lm_prev, Rm, ch, ch2, fmc);
+                rusanov_p<MD>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
             __syncthreads();  // (C) all reads of the right face states done
 #pragma unroll
             for (int d = 0; d < DIN; d++)
@@ -460,12 +571,13 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
 #pragma unroll
             for (int v = 0; v < NV; v++) {
                 fm_prev[v] = dom ? fmc[v] : T(0);
-                Lm_prev[v] = inE ? Lm[v] : T(0);
+                Lm_prev[v] = work ? Lm[v] : T(0);
                 w_prev[v] = w_cur[v];
                 um[v] = u0[v];
                 u0[v] = up[v];
                 up[v] = upp[v];
             }
+            pLm_prev = pLm;
 #pragma unroll
             for (int i = 0; i < 4; i++) {
                 s_prev[i] = src[i];

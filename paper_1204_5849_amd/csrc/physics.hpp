@@ -154,4 +154,67 @@ __device__ __forceinline__ double speed64(double gamma, const double u[NV])
     return fabs(vd) + sqrt(cf2);
 }
 
+// primitive quantities of one state, computed once and shared by the
+// admissibility test, the flux and the fast speed of that state
+template <typename T>
+struct Prim {
+    T ir, vx, vy, vz, bb, p;
+};
+
+template <typename T, bool MIXED>
+__device__ __forceinline__ void prim_of(const Phys<T, MIXED> &ph, const T u[NV], Prim<T> &w)
+{
+    w.ir = Num<T>::rcp(u[RHO]);
+    w.vx = u[MX] * w.ir;
+    w.vy = u[MY] * w.ir;
+    w.vz = u[MZ] * w.ir;
+    w.bb = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
+    w.p = ph.pressure(u, w.ir, w.vx, w.vy, w.vz, T(0.5) * w.bb);
+}
+
+template <typename T>
+__device__ __forceinline__ bool admissible_w(const T u[NV], const Prim<T> &w)
+{
+    return u[RHO] > T(0) && w.p > T(0);
+}
+
+// EGLM flux along D from a state and its primitives
+template <int D, typename T>
+__device__ __forceinline__ void flux_w(const T u[NV], const Prim<T> &w, T ch2, T f[NV])
+{
+    const T v[3] = {w.vx, w.vy, w.vz};
+    const T B[3] = {u[BX], u[BY], u[BZ]};
+    const T me = T(0.5) * w.bb;
+    const T pt = w.p + me;
+    const T vd = v[D], Bd = B[D];
+    const T vb = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
+    f[RHO] = u[MX + D];
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+        f[MX + j] = u[MX + j] * vd - B[j] * Bd;
+    f[MX + D] = f[MX + D] + pt;
+#pragma unroll
+    for (int j = 0; j < 3; j++)
+        f[BX + j] = B[j] * vd - Bd * v[j];
+    f[BX + D] = u[PSI];
+    f[EN] = (u[EN] + pt) * vd - Bd * vb;
+    f[PSI] = ch2 * Bd;
+}
+
+// |v_D| + c_f,D from a state and its primitives
+template <int D, typename T>
+__device__ __forceinline__ T speed_w(const T u[NV], const Prim<T> &w, T gamma)
+{
+    const T a2 = gamma * w.p * w.ir;
+    const T b2 = w.bb * w.ir;
+    const T s = a2 + b2;
+    const T Bd = u[BX + D];
+    T disc = s * s - T(4) * a2 * (Bd * Bd) * w.ir;
+    disc = disc < T(0) ? T(0) : disc;
+    T cf2 = T(0.5) * (s + Num<T>::sqrt_(disc));
+    cf2 = cf2 < T(0) ? T(0) : cf2;
+    const T vd = D == 0 ? w.vx : (D == 1 ? w.vy : w.vz);
+    return fabs(vd) + Num<T>::sqrt_(cf2);
+}
+
 }  // namespace mapk
