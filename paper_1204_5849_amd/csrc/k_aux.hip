@@ -89,12 +89,33 @@ __device__ __forceinline__ int dir_index(int x, int y, int z)
 __device__ __forceinline__ int src_index(int g, int o) { return o >= CLAMP ? o - CLAMP : g + o; }
 
 // ---- same-level copies and physical edges (descriptor src >= 0)
+// Work items of a persistent grid, mapped so that the workgroups on one XCD
+// (workgroups are dealt to the 8 XCDs round robin) walk one contiguous range
+// of the Morton-ordered list: neighbouring blocks then share that XCD's L2.
+__device__ __forceinline__ void xcd_range(int nitems, int &first, int &stride, int &end)
+{
+    const int G = gridDim.x;
+    if (G % 8 != 0 || G < 8) {
+        first = blockIdx.x;
+        stride = G;
+        end = nitems;
+        return;
+    }
+    const int x = blockIdx.x & 7, l = blockIdx.x >> 3, per = G >> 3;
+    const int chunk = (nitems + 7) / 8;
+    first = x * chunk + l;
+    stride = per;
+    end = min(nitems, (x + 1) * chunk);
+}
+
 template <int NDIM, typename T>
 __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
 {
     constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC, BPW = FG<NDIM>::BPW;
     T *U = (T *)a.U;
-    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    int first, stride, end;
+    xcd_range(a.nitems, first, stride, end);
+    for (int item = first; item < end; item += stride) {
         for (int g = threadIdx.x; g < BPW * NGC; g += NTA) {
             const int lb = g / NGC, gi = g - lb * NGC;
             const int slot = a.slot_base + item * BPW + lb;

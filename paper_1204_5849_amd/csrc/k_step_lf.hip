@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
             if (has) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    dst[v] = ub[(size_t)v * P + (k + NG) * XS + q];
+                    dst[v] = ub[v * P + (k + NG) * XS + q];
             } else {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
@@ -200,7 +200,7 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
             if (xhas) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    dst[v] = xb[(size_t)v * P + (k + NG) * XS + xq];
+                    dst[v] = xb[v * P + (k + NG) * XS + xq];
             }
         };
 
@@ -209,19 +209,16 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         load(u0, -1);
         load(up, 0);
         load_x(xc, -1);
-        T Lm_prev[NV], fm_prev[NV], w_prev[NV], s_prev[4];
+        // carried to the next plane: Wc = u - (in-plane flux differences)
+        // + dt/dx_m f(k-1/2) + dt (sources + in-plane resistive terms), the
+        // left state of the face k+1/2, and eta J of the two previous planes
+        T Lm_prev[NV], Wc[NV];
         T pLm_prev = T(1);
-        T rin_prev[4], jm1[3], jm2[3];
+        T jm1[3], jm2[3];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             Lm_prev[v] = T(0);
-            fm_prev[v] = T(0);
-            w_prev[v] = T(0);
-        }
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            s_prev[i] = T(0);
-            rin_prev[i] = T(0);
+            Wc[v] = T(0);
         }
 #pragma unroll
         for (int i = 0; i < 3; i++) {
@@ -517,72 +514,68 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
             }
             __syncthreads();  // (D) in-plane face fluxes published
 
-            T w_cur[NV];
+            // ---- finalise plane k-1 with the face k-1/2: march-axis flux
+            //      difference, march-axis resistive terms, psi damping (MHD-5
+            //      integrated exactly)
+            if (dom && k >= 1 && has) {
+                T o[NV];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    o[v] = Wc[v] - dtdx[MD] * fmc[v];
+                if constexpr (RESIST) {
+                    if constexpr (NDIM == 3) {
+                        o[BX] = o[BX] + dt * ((jc[1] - jm2[1]) * i2d[2]);
+                        o[BY] = o[BY] - dt * ((jc[0] - jm2[0]) * i2d[2]);
+                        o[EN] = o[EN] + dt * ((jc[2] - jm2[2]) * i2d[2]);
+                    } else {
+                        o[BX] = o[BX] - dt * ((jc[1] - jm2[1]) * i2d[1]);
+                        o[BZ] = o[BZ] + dt * ((jc[0] - jm2[0]) * i2d[1]);
+                        o[EN] = o[EN] + dt * ((jc[2] - jm2[2]) * i2d[1]);
+                    }
+                }
+                o[PSI] = o[PSI] * damp;
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    ob[v * P + (k - 1 + NG) * XS + q] = o[v];
+            }
+            // ---- start plane k: in-plane flux differences, the lower face
+            //      k-1/2, EGLM sources and in-plane resistive terms
             if (inI && kI) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     T acc = dtdx[0] * (fin[0][v] - srf[((lb * DIN + 0) * NV + v) * XS + q - 1]);
                     if constexpr (NDIM == 3)
                         acc += dtdx[1] * (fin[1][v] - srf[((lb * DIN + 1) * NV + v) * XS + q - SY]);
-                    w_cur[v] = u0[v] - acc;
+                    Wc[v] = (u0[v] - acc) + dtdx[MD] * fmc[v];
                 }
-            } else {
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    w_cur[v] = T(0);
-            }
-            // ---- finalise plane k-1: march-axis flux difference, sources,
-            //      resistivity, psi damping (MHD-5 integrated exactly)
-            if (dom && k >= 1 && has) {
-                T o[NV];
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    o[v] = w_prev[v] - dtdx[MD] * (fmc[v] - fm_prev[v]);
                 if (a.eglm) {
-                    o[MX] = o[MX] - dt * s_prev[0];
-                    o[MY] = o[MY] - dt * s_prev[1];
-                    o[MZ] = o[MZ] - dt * s_prev[2];
-                    o[EN] = o[EN] - dt * s_prev[3];
+                    Wc[MX] = Wc[MX] - dt * src[0];
+                    Wc[MY] = Wc[MY] - dt * src[1];
+                    Wc[MZ] = Wc[MZ] - dt * src[2];
+                    Wc[EN] = Wc[EN] - dt * src[3];
                 }
                 if constexpr (RESIST) {
-                    T rx, ry, rz, re;
                     if constexpr (NDIM == 3) {
-                        rx = (jc[1] - jm2[1]) * i2d[2] + rin_prev[0];
-                        ry = rin_prev[1] - (jc[0] - jm2[0]) * i2d[2];
-                        rz = rin_prev[2];
-                        re = rin_prev[3] + (jc[2] - jm2[2]) * i2d[2];
+                        Wc[BX] = Wc[BX] + dt * rin[0];
+                        Wc[BY] = Wc[BY] + dt * rin[1];
+                        Wc[BZ] = Wc[BZ] + dt * rin[2];
+                        Wc[EN] = Wc[EN] + dt * rin[3];
                     } else {
-                        rx = -((jc[1] - jm2[1]) * i2d[1]);
-                        ry = rin_prev[0];
-                        rz = (jc[0] - jm2[0]) * i2d[1] - rin_prev[1];
-                        re = rin_prev[2] + (jc[2] - jm2[2]) * i2d[1];
+                        Wc[BY] = Wc[BY] + dt * rin[0];
+                        Wc[BZ] = Wc[BZ] - dt * rin[1];
+                        Wc[EN] = Wc[EN] + dt * rin[2];
                     }
-                    o[BX] = o[BX] + dt * rx;
-                    o[BY] = o[BY] + dt * ry;
-                    o[BZ] = o[BZ] + dt * rz;
-                    o[EN] = o[EN] + dt * re;
                 }
-                o[PSI] = o[PSI] * damp;
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    ob[(size_t)v * P + (k - 1 + NG) * XS + q] = o[v];
             }
             // ---- shift the march-axis registers
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                fm_prev[v] = dom ? fmc[v] : T(0);
                 Lm_prev[v] = work ? Lm[v] : T(0);
-                w_prev[v] = w_cur[v];
                 um[v] = u0[v];
                 u0[v] = up[v];
                 up[v] = upp[v];
             }
             pLm_prev = pLm;
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                s_prev[i] = src[i];
-                rin_prev[i] = rin[i];
-            }
 #pragma unroll
             for (int i = 0; i < 3; i++) {
                 jm2[i] = jm1[i];

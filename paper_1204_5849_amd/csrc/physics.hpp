@@ -47,6 +47,14 @@ __device__ __forceinline__ T lim_minmod(T a, T b)
     return s * m;
 }
 
+// in FP32 the same value is the median of (a, b, 0): the smaller magnitude
+// when a and b share a sign, zero otherwise -- one v_med3_f32 instruction
+template <>
+__device__ __forceinline__ float lim_minmod<float>(float a, float b)
+{
+    return __builtin_amdgcn_fmed3f(a, b, 0.0f);
+}
+
 // limiter selected at run time (uniform across the launch):
 // minmod, van Leer (ab + |ab|)/(a + b), or the literal flux limiter of
 // Sec. 3.1 in ratio-free form phi(a/b) b
@@ -67,7 +75,10 @@ struct Phys {
     T gamma, gm1;
     double gm1d;
 
-    // p = (gamma - 1)(e - rho v^2/2 - B^2/2); ir = 1/rho, v = m ir
+    // p = (gamma - 1)(e - rho v^2/2 - B^2/2); ir = 1/rho, v = m ir.
+    // MIXED: recovered in FP64 from the FP32 conserved variables, whose
+    // products are exact in FP64, so the cancellation at low beta costs no
+    // precision.
     __device__ __forceinline__ T pressure(const T u[NV], T ir, T vx, T vy, T vz, T me) const
     {
         if constexpr (MIXED) {
