@@ -62,6 +62,50 @@ def step_bytes_per_launch(wl, nleaves, word):
     return nleaves * 9 * (P + I) * word
 
 
+# FP operations of the LF block update per leaf cell-update (add, sub, mul,
+# div, sqrt: 1; fused multiply-add: 2), counted from the scheme as the step
+# kernel evaluates it, including the ring of cells one outside the interior
+# that a per-block update must predict (5632 cells per 4096 in 3-D, 320 per
+# 256 in 2-D).  Per predicted cell (3-D): slopes 81, six half-step states
+# 6 x (18 state + 28 primitives + 28 flux) = 444, flux differences 81,
+# u~ 9, six face states 6 x (18 + 28) = 276 -> 891 x 1.375 = 1225.  Per face:
+# primitives 18, two fluxes 56, two fast speeds 28, Rusanov combination 45,
+# max 1 -> 148, three faces per cell -> 444.  Update 81, EGLM sources 33,
+# resistivity 75, psi damping 1.  2-D: (54 + 296 + 54 + 9 + 184) x 1.25 =
+# 746, two faces 296, update 54, sources 26, damping 1.
+FLOPS_PER_CELL = {(3, True): 1860, (3, False): 1785, (2, True): 1123 + 60, (2, False): 1123}
+
+# MI355X vector peak for FP32 (non-packed) and FP64: 256 CUs x 4 SIMDs x
+# 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s
+ALU_PEAK_TFLOPS = 78.6
+
+
+def step_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_step_lf.hip", "physics.hpp", "kernels.hpp", "map_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1204_5849_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per step launch from the committed counter summary, if it was
+    taken on the current step-kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{workload_name}_fp32_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("step_traffic:"):
+            for kv in line.split()[1:]:
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("sources") != step_sources_hash() or "bytes" not in vals:
+        return None
+    return int(vals["bytes"])
+
+
 def time_step_kernel(sim, reps):
     """Average duration of the step kernel alone (HIP events on its stream)."""
     import torch
@@ -100,6 +144,14 @@ def cpu_baseline(seconds_budget=25.0):
             "sample": f"FP64 oracle, 1 thread, {n} full cycle(s) of the Harris sheet at base "
                       f"32^3 with 4 levels ({len(w.keys)} blocks, {cells} leaf cells)",
             "seconds": round(dt, 2)}
+
+
+def cycle_bytes_per_cell(wl, word):
+    """Algorithmic bytes of one whole cycle per leaf cell for a padded-ghost
+    per-block method: the step reads the padded tile and writes the interior,
+    the fill reads and writes the ghost frame: 9 w (3P - I) / I."""
+    P, I = 20 ** wl.ndim, 16 ** wl.ndim
+    return 9 * word * (3 * P - I) / I
 
 
 def rel_l1(a, b):
@@ -173,7 +225,11 @@ def main():
     t_step = time_step_kernel(sim, 10)
     bytes_step = step_bytes_per_launch(wl, sim.sizes.nleaves, word)
     achieved = bytes_step / t_step / 1e9
-    log(f"step kernel {t_step * 1e3:.3f} ms/launch, {achieved:.1f} GB/s algorithmic")
+    fpc = FLOPS_PER_CELL[(wl.ndim, wl.eta > 0)]
+    tflops = nleaf_cells * fpc / t_step / 1e12
+    traffic = measured_traffic(wl.name) if args.precision == "fp32" else None
+    log(f"step kernel {t_step * 1e3:.3f} ms/launch, {achieved:.1f} GB/s algorithmic, "
+        f"{tflops:.2f} TFLOP/s")
 
     result = {
         "metric": METRIC,
@@ -194,13 +250,15 @@ def main():
                    "limiter": wl.limiter, "glm": wl.glm_mode, "eta": wl.eta,
                    "state": args.precision, "launch": "eager batched" if args.eager
                    else "hipGraph, batched persistent", "grids": chosen},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
                      "kernel": "k_step_lf", "kernel_ms": t_step * 1e3,
-                     "bytes_per_launch": bytes_step},
+                     "flops_per_cell_update": fpc, "algorithmic_bytes_per_launch": bytes_step,
+                     "hbm_achieved_GBs": achieved, "hbm_peak_GBs": HBM_PEAK_GBS,
+                     "hbm_frac": achieved / HBM_PEAK_GBS, "step_share_of_cycle": t_step * 1e3 / ms},
+        "hbm_frac_cycle": nleaf_cells * cycle_bytes_per_cell(wl, word) / (ms * 1e-3) / 1e9
+        / HBM_PEAK_GBS,
     }
-    # per-step share of the whole cycle spent in the step kernel
-    result["roofline"]["step_share"] = t_step * 1e3 / ms
 
     if not args.no_plain:
         del sim

@@ -210,15 +210,18 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         load(up, 0);
         load_x(xc, -1);
         // carried to the next plane: Wc = u - (in-plane flux differences)
-        // + dt/dx_m f(k-1/2) + dt (sources + in-plane resistive terms), the
-        // left state of the face k+1/2, and eta J of the two previous planes
-        T Lm_prev[NV], Wc[NV];
+        // + dt (sources + in-plane resistive terms), the flux of the face
+        // k-1/2 (the march-axis difference is taken as a difference, so a
+        // uniform state stays exactly uniform), the left state of the face
+        // k+1/2, and eta J of the two previous planes
+        T Lm_prev[NV], Wc[NV], fm_prev[NV];
         T pLm_prev = T(1);
         T jm1[3], jm2[3];
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             Lm_prev[v] = T(0);
             Wc[v] = T(0);
+            fm_prev[v] = T(0);
         }
 #pragma unroll
         for (int i = 0; i < 3; i++) {
@@ -521,7 +524,7 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                 T o[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    o[v] = Wc[v] - dtdx[MD] * fmc[v];
+                    o[v] = Wc[v] - dtdx[MD] * (fmc[v] - fm_prev[v]);
                 if constexpr (RESIST) {
                     if constexpr (NDIM == 3) {
                         o[BX] = o[BX] + dt * ((jc[1] - jm2[1]) * i2d[2]);
@@ -538,15 +541,15 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                 for (int v = 0; v < NV; v++)
                     ob[v * P + (k - 1 + NG) * XS + q] = o[v];
             }
-            // ---- start plane k: in-plane flux differences, the lower face
-            //      k-1/2, EGLM sources and in-plane resistive terms
+            // ---- start plane k: in-plane flux differences, EGLM sources and
+            //      in-plane resistive terms
             if (inI && kI) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
                     T acc = dtdx[0] * (fin[0][v] - srf[((lb * DIN + 0) * NV + v) * XS + q - 1]);
                     if constexpr (NDIM == 3)
                         acc += dtdx[1] * (fin[1][v] - srf[((lb * DIN + 1) * NV + v) * XS + q - SY]);
-                    Wc[v] = (u0[v] - acc) + dtdx[MD] * fmc[v];
+                    Wc[v] = u0[v] - acc;
                 }
                 if (a.eglm) {
                     Wc[MX] = Wc[MX] - dt * src[0];
@@ -570,6 +573,7 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
             // ---- shift the march-axis registers
 #pragma unroll
             for (int v = 0; v < NV; v++) {
+                fm_prev[v] = dom ? fmc[v] : T(0);
                 Lm_prev[v] = work ? Lm[v] : T(0);
                 um[v] = u0[v];
                 u0[v] = up[v];

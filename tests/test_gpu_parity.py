@@ -266,3 +266,21 @@ def test_status_flags(dev):
     s.cfl()
     st, cnt = s.flags()
     assert st == N.MAP_ENONFINITE and cnt[3] >= 1
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uniform_state_bitwise_amr(dev, ndim, precision):
+    """A uniform state stays exactly uniform over whole cycles (fill,
+    prolongation, step with EGLM sources and resistivity, reflux,
+    restriction) on a 3-level tree, in both precisions."""
+    _say(f"uniform state amr ndim={ndim} {precision}")
+    sims, keys = _tree(ndim, 13 + ndim, "mixed" if ndim == 3 else "outflow")
+    w = W.Workload(name="uni", ndim=ndim, sims=sims, keys=keys, precision=precision,
+                   eta=1e-3 if ndim == 3 else 0.0, glm_mode="fastspeed" if ndim == 3 else "paper",
+                   ic=lambda wl, s, lv, x, y, z, g: [1.2, 0.3, -0.2, 0.1, 0.4, 0.5, -0.6, 0.9, 0.0])
+    s = _sim(w)
+    u0 = s.U.clone()
+    s.graph_run(4)
+    s.sync()
+    assert torch.equal(s.U, u0)
