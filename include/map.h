@@ -92,7 +92,9 @@ typedef struct {
 
 typedef struct {
     size_t state_bytes;      /* bytes of U */
-    size_t workspace_bytes;  /* bytes of the workspace to bind */
+    size_t workspace_bytes;  /* bytes of the workspace to bind (tables, face
+                                fluxes and one shadow copy of the state, which
+                                map_advance, map_graph_run and map_autotune use) */
     int nblocks, nleaves, nsims, max_level, tile_cells, nvar;
     int n_prolong_items, n_reflux_blocks, n_face_buffers;
 } map_sizes;
@@ -154,9 +156,14 @@ map_status map_cfl_dt(map_ctx *ctx, const void *U, map_dt *dt_dev, void *stream)
 
 /* One two-step update of every leaf of every simulation (Sec. 3.1 or 3.2,
  * all directions together, Sec. 3.7) with EGLM sources, resistivity and
- * psi damping, reading padded tiles of U_in and writing interiors of U_out
- * (U_out may equal U_in).  Also stores the fluxes of faces shared with
- * leaves of another level, for map_reflux. */
+ * psi damping, writing the interiors of the leaves of U_out.  Ghost cells
+ * are read where map_fill_ghosts would copy them from (Sec. 4.3): the
+ * interiors of same-level blocks in U_in (leaves, and parents holding the
+ * restriction of their children) and the block's own prolongated ghosts, so
+ * U_in needs up-to-date interiors and prolongated ghost regions only.
+ * U_out must not overlap U_in (MAP_EINVAL): blocks read their neighbours'
+ * old interiors while others are written.  Also stores the fluxes of faces
+ * shared with leaves of another level, for map_reflux. */
 map_status map_step(map_ctx *ctx, const void *U_in, void *U_out, const map_dt *dt_dev,
                     void *stream);
 
@@ -175,13 +182,20 @@ map_status map_totals(map_ctx *ctx, const void *U, double *totals_dev, void *str
  * Returns MAP_ENONFINITE or MAP_ENEGPRESSURE if [3] or [2] is non-zero. */
 map_status map_status_flags(map_ctx *ctx, uint64_t counters[4], void *stream);
 
-/* nsteps full cycles: cfl_dt, step, reflux, restrict, fill_ghosts, with
- * dt kept on the device (the record of the last step is copied to dt_dev
- * if it is not NULL).  Eager launches on `stream`. */
+/* nsteps full cycles: cfl_dt, step, reflux, restrict, then the ghosts the
+ * next step reads from a block's own tile (copies into the frames of the
+ * parents that feed prolongation, prolongation level by level), with dt
+ * kept on the device (the record of the last step is copied to dt_dev if it
+ * is not NULL).  Cycles alternate between U and the workspace's shadow
+ * state; an odd nsteps ends with one device copy back into U.  On return U
+ * holds the interiors of every block and its prolongated ghosts; the
+ * same-level ghost regions of leaves hold unspecified values
+ * (map_fill_ghosts refreshes them).  Eager launches on `stream`. */
 map_status map_advance(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
 
-/* Same cycle as map_advance, captured once per U into a HIP graph and
- * replayed nsteps times on `stream`. */
+/* Same cycles and result as map_advance: the pair of cycles U -> shadow ->
+ * U is captured once per U into a HIP graph and replayed nsteps / 2 times on
+ * `stream`; an odd nsteps adds one eager cycle and the copy back. */
 map_status map_graph_run(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
 
 /* MAP_LAUNCH_BATCHED: one launch per stage over the joint work list of all
@@ -192,8 +206,9 @@ map_status map_set_launch(map_ctx *ctx, int mode, int grid_step, int grid_fill);
 
 /* Time the batched step and fill launches over a set of grid sizes on U with
  * HIP events and keep the fastest (project autotuner); writes the chosen
- * sizes to chosen[2] if not NULL.  Synchronises `stream`; U is overwritten
- * with one extra step per trial. */
+ * sizes to chosen[2] if not NULL.  Synchronises `stream`.  The trial steps
+ * write the shadow state; U's interiors are not changed (ghost frames of
+ * parents that feed prolongation are rewritten with the same values). */
 map_status map_autotune(map_ctx *ctx, void *U, int *chosen, void *stream);
 
 const char *map_last_error(void);

@@ -51,25 +51,31 @@ hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
 bool fp64(const map_ctx *c) { return c->p.precision == MAP_FP64; }
 
-map_status run_fill(map_ctx *c, void *U, hipStream_t s)
+// Ghost fill: same-level copies, then prolongation level by level (coarse to
+// fine).  `all`: the copies fill every slot's ghost frame; otherwise only
+// the frames the prolongation reads (the step reads same-level neighbour
+// interiors in place).
+map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all)
 {
     FillArgs a{};
     a.U = U;
     a.desc = dptr<Desc>(c, c->ws.desc);
     a.blk = dptr<BlockRec>(c, c->ws.blocks);
     a.parent = dptr<int32_t>(c, c->ws.parent);
+    a.copy_list = all ? nullptr : dptr<int32_t>(c, c->ws.frame_list);
+    const int ncopy = all ? c->nslots : (int)c->frame_list.size();
     const int bpw = fill_blocks_per_group(c->nd);
     if (c->launch_mode == MAP_LAUNCH_PER_BLOCK) {
-        for (int sl = 0; sl < c->nslots; sl++) {
-            a.slot_base = sl;
-            a.slot_end = sl + 1;
+        for (int i = 0; i < ncopy; i++) {
+            a.slot_base = i;
+            a.slot_end = i + 1;
             a.nitems = 1;
             HIPCHK(launch_fill_copy(c->nd, fp64(c), a, 1, s));
         }
-    } else {
+    } else if (ncopy > 0) {
         a.slot_base = 0;
-        a.slot_end = c->nslots;
-        a.nitems = (c->nslots + bpw - 1) / bpw;
+        a.slot_end = ncopy;
+        a.nitems = (ncopy + bpw - 1) / bpw;
         HIPCHK(launch_fill_copy(c->nd, fp64(c), a, c->grid_fill, s));
     }
     for (int l = 2; l <= c->lmax; l++) {
@@ -143,6 +149,7 @@ map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, h
     a.dt = dt;
     a.lvl_dx = dptr<double>(c, c->ws.lvl_dx);
     a.fbidx = dptr<int32_t>(c, c->ws.fbidx);
+    a.desc = dptr<Desc>(c, c->ws.desc);
     a.fbuf = c->wsp + c->ws.fbuf;
     a.cnt = dptr<unsigned long long>(c, c->ws.counters);
     a.gamma = c->p.gamma;
@@ -190,19 +197,41 @@ map_status run_reflux(map_ctx *c, void *U, const map_dt *dt, hipStream_t s)
     return MAP_OK;
 }
 
-map_status run_cycle(map_ctx *c, void *U, hipStream_t s)
+// one cycle from Uin to Uout (Fig. 1): dt, update of every leaf, reflux,
+// restriction, and the ghosts the next update reads from its own tile
+map_status run_cycle(map_ctx *c, const void *Uin, void *Uout, hipStream_t s)
 {
     map_dt *dt = dptr<map_dt>(c, c->ws.dt);
     map_status st;
-    if ((st = run_cfl(c, U, nullptr, s)) != MAP_OK)
+    if ((st = run_cfl(c, Uin, nullptr, s)) != MAP_OK)
         return st;
-    if ((st = run_step(c, U, U, dt, s)) != MAP_OK)
+    if ((st = run_step(c, Uin, Uout, dt, s)) != MAP_OK)
         return st;
-    if ((st = run_reflux(c, U, dt, s)) != MAP_OK)
+    if ((st = run_reflux(c, Uout, dt, s)) != MAP_OK)
         return st;
-    if ((st = run_restrict(c, U, s)) != MAP_OK)
+    if ((st = run_restrict(c, Uout, s)) != MAP_OK)
         return st;
-    return run_fill(c, U, s);
+    return run_fill(c, Uout, s, false);
+}
+
+size_t state_bytes(const map_ctx *c) { return (size_t)c->nslots * NV * c->tile * c->word; }
+
+void *shadow(map_ctx *c) { return c->wsp + c->ws.shadow; }
+
+// n cycles alternating between U and the workspace's shadow state; an odd
+// count ends with one copy of the shadow back into U
+map_status run_cycles(map_ctx *c, void *U, int n, hipStream_t s)
+{
+    map_status st;
+    void *S2 = shadow(c);
+    for (int i = 0; i < n; i++) {
+        const bool even = (i & 1) == 0;
+        if ((st = run_cycle(c, even ? U : S2, even ? S2 : U, s)) != MAP_OK)
+            return st;
+    }
+    if (n & 1)
+        HIPCHK(hipMemcpyAsync(U, S2, state_bytes(c), hipMemcpyDeviceToDevice, s));
+    return MAP_OK;
 }
 
 void drop_graph(map_ctx *c)
@@ -249,7 +278,7 @@ map_status map_query(const map_ctx *c, map_sizes *sz, int32_t *slot_of_key)
 {
     if (!c || !sz)
         return fail(MAP_EINVAL, "null argument");
-    sz->state_bytes = (size_t)c->nslots * NV * c->tile * c->word;
+    sz->state_bytes = state_bytes(c);
     sz->workspace_bytes = c->ws.total;
     sz->nblocks = c->nslots;
     sz->nleaves = c->nleaves;
@@ -312,6 +341,7 @@ map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
     HIPCHK(up(c->ws.leaves, c->leaves.data(), c->leaves.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.restrict_list, c->restrict_list.data(), c->restrict_list.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.prolong_list, c->prolong_list.data(), c->prolong_list.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.frame_list, c->frame_list.data(), c->frame_list.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.reflux_slots, c->reflux_slots.data(), c->reflux_slots.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.reflux_start, c->reflux_start.data(), c->reflux_start.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.reflux_recs, c->reflux_recs.data(), c->reflux_recs.size() * sizeof(RefluxRec)));
@@ -342,7 +372,7 @@ map_status map_fill_ghosts(map_ctx *c, void *U, void *stream)
         return st;
     if (!U)
         return fail(MAP_EINVAL, "null U");
-    return run_fill(c, U, S(stream));
+    return run_fill(c, U, S(stream), true);
 }
 
 map_status map_restrict(map_ctx *c, void *U, void *stream)
@@ -389,6 +419,12 @@ map_status map_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt_de
         return st;
     if (!Uin || !Uout || !dt_dev)
         return fail(MAP_EINVAL, "null U or dt");
+    {
+        const char *i0 = static_cast<const char *>(Uin), *o0 = static_cast<const char *>(Uout);
+        const size_t nb = state_bytes(c);
+        if (i0 < o0 + nb && o0 < i0 + nb)
+            return fail(MAP_EINVAL, "Uout overlaps Uin (the update reads neighbour cells of Uin)");
+    }
     return run_step(c, Uin, Uout, dt_dev, S(stream));
 }
 
@@ -453,9 +489,8 @@ map_status map_advance(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *st
     if (!U || nsteps < 0)
         return fail(MAP_EINVAL, "null U or negative step count");
     hipStream_t s = S(stream);
-    for (int i = 0; i < nsteps; i++)
-        if ((st = run_cycle(c, U, s)) != MAP_OK)
-            return st;
+    if ((st = run_cycles(c, U, nsteps, s)) != MAP_OK)
+        return st;
     if (dt_dev && nsteps > 0)
         HIPCHK(hipMemcpyAsync(dt_dev, c->wsp + c->ws.dt, sizeof(map_dt) * c->sims.size(),
                               hipMemcpyDeviceToDevice, s));
@@ -478,8 +513,11 @@ map_status map_graph_run(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *
             c->cap_stream = cs;
         }
         hipStream_t cs = S(c->cap_stream);
+        // two cycles, U -> shadow -> U
         HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-        st = run_cycle(c, U, cs);
+        st = run_cycle(c, U, shadow(c), cs);
+        if (st == MAP_OK)
+            st = run_cycle(c, shadow(c), U, cs);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(cs, &g);
         if (st != MAP_OK) {
@@ -497,8 +535,10 @@ map_status map_graph_run(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *
         c->graph_exec = ex;
         c->graph_U = U;
     }
-    for (int i = 0; i < nsteps; i++)
+    for (int i = 0; i + 1 < nsteps; i += 2)
         HIPCHK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(c->graph_exec), s));
+    if ((nsteps & 1) && (st = run_cycles(c, U, 1, s)) != MAP_OK)
+        return st;
     if (dt_dev && nsteps > 0)
         HIPCHK(hipMemcpyAsync(dt_dev, c->wsp + c->ws.dt, sizeof(map_dt) * c->sims.size(),
                               hipMemcpyDeviceToDevice, s));
@@ -533,7 +573,7 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
     const int bpw = step_blocks_per_group(c->nd, c->p.scheme);
     const int nstep = (c->nleaves + bpw - 1) / bpw;
     const int fbpw = fill_blocks_per_group(c->nd);
-    const int nfill = (c->nslots + fbpw - 1) / fbpw;
+    const int nfill = ((int)c->frame_list.size() + fbpw - 1) / fbpw;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -564,7 +604,7 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
     float best_t = 1e30f;
     for (int g : cands) {
         c->grid_step = g;
-        float t = time_it([&] { return run_step(c, U, U, dt, s); });
+        float t = time_it([&] { return run_step(c, U, shadow(c), dt, s); });
         if (t < best_t) {
             best_t = t;
             best_step = g;
@@ -578,7 +618,7 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
     best_t = 1e30f;
     for (int g : fc) {
         c->grid_fill = g;
-        float t = time_it([&] { return run_fill(c, U, s); });
+        float t = time_it([&] { return run_fill(c, U, s, false); });
         if (t < best_t) {
             best_t = t;
             best_fill = g;

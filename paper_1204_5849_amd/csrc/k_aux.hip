@@ -11,6 +11,7 @@
 // memory-bound kernel).
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "tile.hpp"
 
 #pragma clang fp contract(off)
 
@@ -28,14 +29,6 @@ struct FG<3> {
                          NI = NB * NB * NB;
 };
 constexpr int NTA = 256;
-
-template <int NDIM>
-__device__ __forceinline__ int lin(int x, int y, int z)
-{
-    if constexpr (NDIM == 3)
-        return ((z + NG) * PD + (y + NG)) * PD + (x + NG);
-    return (y + NG) * PD + (x + NG);
-}
 
 // g-th ghost cell of a block, enumerated in the padded tile's linear order
 // by regions: the ghost planes/rows below and above, then the side strips
@@ -77,17 +70,6 @@ __device__ __forceinline__ void ghost_xyz(int g, int &x, int &y, int &z)
     }
 }
 
-template <int NDIM>
-__device__ __forceinline__ int dir_index(int x, int y, int z)
-{
-    int dx = x < 0 ? -1 : (x >= NB ? 1 : 0);
-    int dy = y < 0 ? -1 : (y >= NB ? 1 : 0);
-    int dz = NDIM == 3 ? (z < 0 ? -1 : (z >= NB ? 1 : 0)) : 0;
-    return (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
-}
-
-__device__ __forceinline__ int src_index(int g, int o) { return o >= CLAMP ? o - CLAMP : g + o; }
-
 // ---- same-level copies and physical edges (descriptor src >= 0)
 // Work items of a persistent grid, mapped so that the workgroups on one XCD
 // (workgroups are dealt to the 8 XCDs round robin) walk one contiguous range
@@ -118,9 +100,10 @@ __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
     for (int item = first; item < end; item += stride) {
         for (int g = threadIdx.x; g < BPW * NGC; g += NTA) {
             const int lb = g / NGC, gi = g - lb * NGC;
-            const int slot = a.slot_base + item * BPW + lb;
-            if (slot >= a.slot_end)
+            const int i = a.slot_base + item * BPW + lb;
+            if (i >= a.slot_end)
                 break;
+            const int slot = a.copy_list ? a.copy_list[i] : i;
             int x, y, z;
             ghost_xyz<NDIM>(gi, x, y, z);
             const Desc ds = a.desc[(size_t)slot * NDIR + dir_index<NDIM>(x, y, z)];

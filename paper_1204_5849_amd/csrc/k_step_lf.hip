@@ -13,14 +13,19 @@
 //     of a block instead of the whole padded tile (a 20^3 x 9 FP32 tile would
 //     not fit in 160 KB);
 //   * each face flux is evaluated once; the next plane is prefetched from
-//     HBM while the current one is processed; every HBM access is a
-//     contiguous row of the structure-of-arrays tile.
+//     HBM while the current one is processed;
+//   * ghost cells are read where the ghost descriptors point (Sec. 4.3): a
+//     same-level neighbour's interior in U_in, with periodic wrap or outflow
+//     clamping, or the block's own prolongated ghost region.  So no copy
+//     pass fills same-level ghosts before the update, and U_out must not
+//     alias U_in.
 // 2-D workgroups hold 14 blocks, 3-D workgroups one block (5 waves).  A
 // persistent grid strides over the work list.
 #include <type_traits>
 
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "tile.hpp"
 
 namespace mapk {
 
@@ -83,6 +88,13 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
     __shared__ T srf[BPW * DIN * NV * XS];
     __shared__ T spr[BPW * DIN * XS];
     __shared__ T sj[RESIST ? BPW * 5 * XS : 1];
+    // per thread: where its column (and its load-only cell) reads the plane
+    // regions -2, -1, the interior (plane 0; plane k adds k XS), NB, NB+1
+    constexpr int NXT = NDIM == 3 ? SG<3>::NX : SG<2>::NX * BPW;
+    // (element offsets from Uin, so that the loads stay in the global
+    // address space)
+    __shared__ size_t gcol[5 * SG<NDIM>::NT];
+    __shared__ size_t gxc[5 * NXT];
 
     // ---- this thread's column and its extra (load-only) cell
     const int t = threadIdx.x;
@@ -114,10 +126,9 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         qy = 0;
     }
     const int q = (NDIM == 3 ? (qy + NG) * PD : 0) + qx + NG;
-    int xq = -1, xlb = 0;
+    int xq = -1, xlb = 0, ex = 0, ey = 0;
     if constexpr (NDIM == 3) {
         if (t < SG<3>::NX) {
-            int ex, ey;
             if (t < PD) {
                 ex = t - NG;
                 ey = -NG;
@@ -141,6 +152,7 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         if (t < SG<2>::NX * BPW) {
             xlb = t >> 1;
             xq = (t & 1) ? PD - 1 : 0;
+            ex = xq - NG;
         }
     }
     const bool xI = qx >= 0 && qx < NB;
@@ -179,15 +191,37 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         }
         const T dt = (T)rec.dt, ch = (T)rec.ch, ch2 = (T)(rec.ch * rec.ch), damp = (T)rec.damp;
         const T eta = (T)a.eta;
-        const T *ub = Uin + (size_t)slot * NV * P;
-        const T *xb = Uin + (size_t)xslot * NV * P;
         T *ob = Uout + (size_t)slot * NV * P;
+
+        auto set_src = [&](size_t *tab, int stride, int sl, int cx, int cy) {
+            const int zr[5] = {-2, -1, 0, NB, NB + 1};
+#pragma unroll
+            for (int r = 0; r < 5; r++) {
+                if constexpr (NDIM == 3)
+                    tab[r * stride] = cell_src<3>(a.desc, sl, cx, cy, zr[r]);
+                else
+                    tab[r * stride] = cell_src<2>(a.desc, sl, cx, zr[r], 0);
+            }
+        };
+        // k is the same for the whole workgroup: the region choice is uniform
+        auto src_of = [&](const size_t *tab, int stride, int k) -> const T * {
+            if (k < 0)
+                return Uin + tab[(k + 2) * stride];
+            if (k < NB)
+                return Uin + tab[2 * stride] + k * XS;
+            return Uin + tab[(k - NB + 3) * stride];
+        };
+        if (has)
+            set_src(gcol + t, SG<NDIM>::NT, slot, qx, qy);
+        if (xhas)
+            set_src(gxc + t, NXT, xslot, ex, ey);
 
         auto load = [&](T(&dst)[NV], int k) {
             if (has) {
+                const T *p = src_of(gcol + t, SG<NDIM>::NT, k);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    dst[v] = ub[v * P + (k + NG) * XS + q];
+                    dst[v] = p[v * P];
             } else {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
@@ -198,9 +232,10 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         };
         auto load_x = [&](T(&dst)[NV], int k) {
             if (xhas) {
+                const T *p = src_of(gxc + t, NXT, k);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    dst[v] = xb[v * P + (k + NG) * XS + xq];
+                    dst[v] = p[v * P];
             }
         };
 

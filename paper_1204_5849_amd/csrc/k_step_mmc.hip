@@ -5,12 +5,15 @@
 // together (Sec. 3.7), followed by the same EGLM sources and psi damping as
 // the LF update.
 //
-// One workgroup per block (256 threads).  Split fluxes of one dimension are
-// staged in LDS at a time (u and u~ for the whole padded tile would not fit
-// together with them); the split fluxes of the last predictor dimension are
-// reused by the first corrector dimension.
+// One workgroup per block (256 threads).  The padded tile of u^n is staged
+// in LDS first, its ghost cells read where the ghost descriptors point (a
+// same-level neighbour's interior in U_in, or the block's own prolongated
+// ghosts), so U_out must not alias U_in.  Split fluxes of one dimension are
+// staged in LDS at a time; the split fluxes of the last predictor dimension
+// are reused by the first corrector dimension.
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "tile.hpp"
 
 namespace mapk {
 
@@ -29,6 +32,7 @@ __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
     __shared__ T sfp[NV * T2], sfm[NV * T2];
     __shared__ T stp[NV * E2], stm[NV * E2];
     __shared__ T sfh[NV * F2];
+    __shared__ T su[NV * T2];
 
     Phys<T, MIXED> ph;
     ph.gamma = (T)a.gamma;
@@ -54,8 +58,15 @@ __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
         }
         const T dt = (T)rec.dt, ch = (T)rec.ch, ch2 = (T)(rec.ch * rec.ch), damp = (T)rec.damp;
         const T alpha = (T)rec.alpha;
-        const T *ub = Uin + (size_t)slot * NV * T2;
         T *ob = Uout + (size_t)slot * NV * T2;
+        for (int c = t; c < T2; c += NT) {
+            const T *p = Uin + cell_src<2>(a.desc, slot, c % PD - NG, c / PD - NG, 0);
+#pragma unroll
+            for (int v = 0; v < NV; v++)
+                su[v * T2 + c] = p[v * T2];
+        }
+        __syncthreads();
+        const T *ub = su;
 
         // split fluxes of u along D on the padded tile -> sfp, sfm
         auto split_u = [&](auto dc) {
@@ -215,7 +226,6 @@ __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
                 o[EN] = o[EN] - dt * bgp;
             }
             o[PSI] = o[PSI] * damp;
-            __syncthreads();  // every thread has read u^n of this block
 #pragma unroll
             for (int v = 0; v < NV; v++)
                 ob[v * T2 + c] = o[v];

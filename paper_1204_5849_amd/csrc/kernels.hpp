@@ -17,6 +17,7 @@ struct StepArgs {
     const map_dt *dt;
     const double *lvl_dx;
     const int32_t *fbidx;
+    const Desc *desc;       // ghost descriptors: neighbour cells are read from Uin in place
     void *fbuf;
     unsigned long long *cnt;
     double gamma, eta;
@@ -28,8 +29,9 @@ struct FillArgs {
     const Desc *desc;
     const BlockRec *blk;
     const int32_t *parent;
-    const int32_t *list;   // prolongation: slots; copy: unused
-    int slot_base, slot_end, nitems;
+    const int32_t *list;       // prolongation: slots of the launch
+    const int32_t *copy_list;  // copies: slots (null: slot = index)
+    int slot_base, slot_end, nitems;  // copies: index range [slot_base, slot_end)
 };
 
 struct RestrictArgs {

@@ -350,6 +350,19 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
         }
     }
     c->prolong_off[lmax + 1] = (int)c->prolong_list.size();
+    // parents whose padded tiles the prolongation reads: the update reads
+    // same-level neighbour interiors in place, so within a cycle only these
+    // ghost frames are filled by copies
+    {
+        std::vector<char> mark(n, 0);
+        for (int s : c->prolong_list)
+            if (c->parent[s] >= 0)
+                mark[c->parent[s]] = 1;
+        c->frame_list.clear();
+        for (int s = 0; s < n; s++)
+            if (mark[s])
+                c->frame_list.push_back(s);
+    }
 
     // ---- reflux: coarse leaf faces whose same-level neighbour has children
     c->fbidx.assign((size_t)n * 6, -1);
@@ -435,6 +448,7 @@ void map_plan_layout(map_ctx *c)
     L.leaves = take((size_t)c->nleaves * sizeof(int32_t));
     L.restrict_list = take(c->restrict_list.size() * sizeof(int32_t));
     L.prolong_list = take(c->prolong_list.size() * sizeof(int32_t));
+    L.frame_list = take(c->frame_list.size() * sizeof(int32_t));
     L.reflux_slots = take(c->reflux_slots.size() * sizeof(int32_t));
     L.reflux_start = take(c->reflux_start.size() * sizeof(int32_t));
     L.reflux_recs = take(c->reflux_recs.size() * sizeof(RefluxRec));
@@ -445,5 +459,6 @@ void map_plan_layout(map_ctx *c)
     L.tot_part = take((size_t)c->nleaves * NV * sizeof(double));
     L.counters = take(4 * sizeof(unsigned long long));
     L.fbuf = take((size_t)c->nfb * NV * c->face_cells() * c->word);
+    L.shadow = take(n * NV * (size_t)c->tile * c->word);
     L.total = o;
 }

@@ -27,6 +27,8 @@ struct map_ctx {
     std::vector<int> restrict_off;         // [lmax + 1] offsets by level
     std::vector<int32_t> prolong_list;     // slots with prolongated ghosts, by level
     std::vector<int> prolong_off;          // [lmax + 2]
+    std::vector<int32_t> frame_list;       // parents of prolong_list slots (their ghost
+                                           // frames feed the prolongation), slot order
     std::vector<int32_t> reflux_slots;     // coarse leaves with reflux faces
     std::vector<int32_t> reflux_start;     // [n + 1] into reflux_recs
     std::vector<mapk::RefluxRec> reflux_recs;

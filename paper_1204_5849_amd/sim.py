@@ -108,8 +108,10 @@ class Simulation:
         N.map_cfl_dt(self.ctx, self.U, self.dt, self.sp)
         return self.dt
 
-    def step(self, Uout=None):
-        N.map_step(self.ctx, self.U, self.U if Uout is None else Uout, self.dt, self.sp)
+    def step(self, Uout):
+        """One update of every leaf from self.U into Uout (a separate tensor of
+        the same shape: the update reads neighbour interiors of self.U)."""
+        N.map_step(self.ctx, self.U, Uout, self.dt, self.sp)
 
     def reflux(self):
         N.map_reflux(self.ctx, self.U, self.dt, self.sp)

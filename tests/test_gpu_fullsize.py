@@ -93,15 +93,15 @@ def test_harris_full_size_sampled_step(dev, orc, precision, tol):
     _say(f"harris 128^3 L4 {precision}: load, autotune, one step launch")
     sim = Simulation(w, precision=precision)
     sim.load_initial()
-    u0 = sim.U.clone()
-    sim.autotune()
-    sim.U.copy_(u0)
-    del u0
+    sim.autotune()  # trial steps write the shadow state; U's interiors are kept
     sim.sync()
     rec = torch.tensor([[2.0e-4, 1.3, math.exp(-2.0e-4 * 1.3 / 0.18), 1.3]], dtype=torch.float64,
                        device=sim.device)
-    N.map_step(sim.ctx, sim.U, sim.U, rec, sim.sp)
+    out = torch.zeros_like(sim.U)
+    torch.cuda.synchronize()  # rec and out are written on torch's stream
+    N.map_step(sim.ctx, sim.U, out, rec, sim.sp)
     sim.sync()
+    sim.U = out
     p = orc.params_from_workload(w)
     orec = orc.make_dtrec(*rec.cpu().numpy()[0].tolist())
     picks = _pick_interior_leaves(w, sim.ctx)
@@ -129,6 +129,7 @@ def test_uniform_state_full_grid(dev, precision):
     sim.load_initial()
     u0 = sim.U.clone()
     sim.graph_run(3)
+    sim.fill()
     sim.sync()
     assert torch.equal(sim.U, u0)
 
