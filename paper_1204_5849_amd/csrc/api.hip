@@ -160,6 +160,8 @@ map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, h
     auto launch = [&](const StepArgs &x, int grid) -> hipError_t {
         if (c->p.scheme == MAP_MMC)
             return launch_step_mmc(c->nd, fp64(c), x, 0.0, grid, s);
+        if (c->nd == 3)
+            return launch_step_lf3(fp64(c), resist, x, grid, s);
         return launch_step_lf(c->nd, fp64(c), resist, x, grid, s);
     };
     const int bpw = step_blocks_per_group(c->nd, c->p.scheme);

@@ -1,163 +1,75 @@
-// k_step_lf.hip -- the TVD-LF block update (paper Sec. 3.2, all directions
+// k_step_lf.hip -- the TVD-LF block update (paper Sec. 3.2, both directions
 // together as in Sec. 3.7) with the EGLM source terms (Sec. 2), uniform
-// resistivity (Sec. 3.5) and exact psi damping, for every leaf of a work list.
+// resistivity (Sec. 3.5) and exact psi damping, for 2-D leaf blocks (the
+// 3-D kernel is in k_step_lf3.hip).
 //
-// Layout and schedule (gfx950): each workgroup owns whole blocks.  Threads own
-// the columns of the block's padded cross-section (x in 2-D, x-y in 3-D) and
-// march along the last axis (y in 2-D, z in 3-D), one plane per iteration:
-//   * the march-axis neighbours of a cell (slopes, the half-step flux, the
-//     face between planes, source and resistive differences) stay in
-//     registers of the owning thread;
-//   * in-plane neighbours are exchanged through LDS one plane at a time
-//     (state, right face states, face fluxes, eta J), so LDS holds one plane
-//     of a block instead of the whole padded tile (a 20^3 x 9 FP32 tile would
-//     not fit in 160 KB);
-//   * each face flux is evaluated once; the next plane is prefetched from
-//     HBM while the current one is processed;
+// Layout and schedule (gfx950): a workgroup of 256 threads holds 14 blocks,
+// 18 columns each (x = -1 .. 16: the interior and the cell on each side
+// whose face states feed the block's x faces).  Threads march along y, one
+// row per iteration:
+//   * y neighbours (slopes, the half-step flux, the face between rows,
+//     source and resistive differences) stay in the thread's registers;
+//   * x neighbours are exchanged through LDS one row at a time (state, right
+//     face states, face fluxes, eta J); the outer cells x = -2 and x = 17
+//     are only loaded, by the first threads, one row ahead;
 //   * ghost cells are read where the ghost descriptors point (Sec. 4.3): a
 //     same-level neighbour's interior in U_in, with periodic wrap or outflow
-//     clamping, or the block's own prolongated ghost region.  So no copy
-//     pass fills same-level ghosts before the update, and U_out must not
-//     alias U_in.
-// 2-D workgroups hold 14 blocks, 3-D workgroups one block (5 waves).  A
-// persistent grid strides over the work list.
+//     clamping, or the block's own prolongated ghost region, so no copy pass
+//     fills same-level ghosts before the update and U_out must not alias
+//     U_in;
+//   * each face flux is evaluated once; the next row is prefetched from HBM
+//     while the current one is processed.
+// A persistent grid strides over the leaf list.
 #include <type_traits>
 
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "step_common.hpp"
 #include "tile.hpp"
 
 namespace mapk {
 
-// Lane layout.  Only the columns whose face states feed a face compute: the
-// ring one cell outside the interior, minus its corners in 3-D (which no
-// face reads), i.e. 18 columns per 2-D block and 320 = 5 waves per 3-D block.
-// The remaining cells of the padded plane (outer ring, 3-D ring corners)
-// are only loaded, by the first threads, one plane ahead.
-template <int NDIM>
-struct SG;
-template <>
-struct SG<2> {
-    static constexpr int XS = PD, BPW = 14, NT = 256, NCOL = NB + 2, NX = 2;
-};
-template <>
-struct SG<3> {
-    static constexpr int XS = PD * PD, BPW = 1, NT = 320, NCOL = 320, NX = 80;
-};
+namespace {
+constexpr int XS2 = PD;            // row stride
+constexpr int P2 = PD * PD;        // padded tile cells
+constexpr int BPW2 = 14;           // blocks per workgroup
+constexpr int NT2 = 256;           // threads
+constexpr int NCOL2 = NB + 2;      // computing columns per block
+constexpr int NXT2 = 2 * BPW2;     // load-only cells (x = -2, x = 17) per row
+}  // namespace
 
-// Rusanov flux (Equ:LFFlux) with alpha = max of the two fast speeds for the
-// MHD components and c_h for the GLM pair (B_D, psi); the pressures of both
-// states are given (computed once when the states were formed)
-template <int D, typename T>
-__device__ __forceinline__ void rusanov_p(const T L[NV], T pL, const T R[NV], T pR, T gamma,
-                                          T ch, T ch2, T f[NV])
+template <typename T, bool MIXED, bool RESIST, int LIM>
+__global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
 {
-    Prim<T> wL, wR;
-    wL.ir = Num<T>::rcp(L[RHO]);
-    wL.vx = L[MX] * wL.ir;
-    wL.vy = L[MY] * wL.ir;
-    wL.vz = L[MZ] * wL.ir;
-    wL.bb = L[BX] * L[BX] + L[BY] * L[BY] + L[BZ] * L[BZ];
-    wL.p = pL;
-    wR.ir = Num<T>::rcp(R[RHO]);
-    wR.vx = R[MX] * wR.ir;
-    wR.vy = R[MY] * wR.ir;
-    wR.vz = R[MZ] * wR.ir;
-    wR.bb = R[BX] * R[BX] + R[BY] * R[BY] + R[BZ] * R[BZ];
-    wR.p = pR;
-    T FL[NV], FR[NV];
-    flux_w<D>(L, wL, ch2, FL);
-    flux_w<D>(R, wR, ch2, FR);
-    const T sL = speed_w<D>(L, wL, gamma), sR = speed_w<D>(R, wR, gamma);
-    const T al = sL > sR ? sL : sR;
-#pragma unroll
-    for (int k = 0; k < NV; k++) {
-        const T ak = (k == BX + D || k == PSI) ? ch : al;
-        f[k] = T(0.5) * (FL[k] + FR[k]) - T(0.5) * ak * (R[k] - L[k]);
-    }
-}
-
-template <int NDIM, typename T, bool MIXED, bool RESIST>
-__global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
-{
-    constexpr int XS = SG<NDIM>::XS, BPW = SG<NDIM>::BPW, DIN = NDIM - 1, MD = NDIM - 1;
-    constexpr int P = XS * PD;
-    constexpr int FC = NDIM == 3 ? NB * NB : NB;
-    constexpr int SY = PD;  // in-plane y stride (3-D)
-    __shared__ T su[BPW * NV * XS];
-    __shared__ T srf[BPW * DIN * NV * XS];
-    __shared__ T spr[BPW * DIN * XS];
+    constexpr int XS = XS2, BPW = BPW2, P = P2, FC = NB;
+    constexpr int SUB = BPW * NV * XS;
+    __shared__ T su[2 * SUB];             // state of rows k and k-1 (by parity)
+    __shared__ T srf[BPW * NV * XS];      // right face states, then fluxes
+    __shared__ T spr[BPW * XS];           // pressures of those face states
     __shared__ T sj[RESIST ? BPW * 5 * XS : 1];
-    // per thread: where its column (and its load-only cell) reads the plane
-    // regions -2, -1, the interior (plane 0; plane k adds k XS), NB, NB+1
-    constexpr int NXT = NDIM == 3 ? SG<3>::NX : SG<2>::NX * BPW;
-    // (element offsets from Uin, so that the loads stay in the global
-    // address space)
-    __shared__ size_t gcol[5 * SG<NDIM>::NT];
-    __shared__ size_t gxc[5 * NXT];
+    // per thread: where its column (and its load-only cell) reads the row
+    // regions -2, -1, the interior (row 0; row k adds k XS), NB, NB+1, as
+    // element offsets from Uin (the loads stay in the global address space)
+    __shared__ size_t gcol[5 * NT2];
+    __shared__ size_t gxc[5 * NXT2];
 
     // ---- this thread's column and its extra (load-only) cell
     const int t = threadIdx.x;
-    int lb, qx, qy;
-    bool lane;
-    if constexpr (NDIM == 3) {
-        lb = 0;
-        lane = t < SG<3>::NCOL;
-        if (t < NB) {
-            qx = t;
-            qy = -1;
-        } else if (t < NB + NB * (NB + 2)) {
-            const int r = t - NB;
-            qy = r / (NB + 2);
-            qx = r - qy * (NB + 2) - 1;
-        } else {
-            qx = t - NB - NB * (NB + 2);
-            qy = NB;
-        }
-    } else {
-        lb = t / SG<2>::NCOL;
-        lane = lb < BPW;
-        qx = t - lb * SG<2>::NCOL - 1;
-        qy = 0;
-    }
+    int lb = t / NCOL2;
+    const bool lane = lb < BPW;
+    int qx = t - lb * NCOL2 - 1;
     if (!lane) {
         lb = 0;
         qx = 0;
-        qy = 0;
     }
-    const int q = (NDIM == 3 ? (qy + NG) * PD : 0) + qx + NG;
-    int xq = -1, xlb = 0, ex = 0, ey = 0;
-    if constexpr (NDIM == 3) {
-        if (t < SG<3>::NX) {
-            if (t < PD) {
-                ex = t - NG;
-                ey = -NG;
-            } else if (t < 2 * PD) {
-                ex = t - PD - NG;
-                ey = NB + 1;
-            } else if (t < 2 * PD + NB + 2) {
-                ex = -NG;
-                ey = t - 2 * PD - 1;
-            } else if (t < 2 * PD + 2 * (NB + 2)) {
-                ex = NB + 1;
-                ey = t - 2 * PD - (NB + 2) - 1;
-            } else {
-                const int c = t - 2 * PD - 2 * (NB + 2);
-                ex = (c & 1) ? NB : -1;
-                ey = (c & 2) ? NB : -1;
-            }
-            xq = (ey + NG) * PD + ex + NG;
-        }
-    } else {
-        if (t < SG<2>::NX * BPW) {
-            xlb = t >> 1;
-            xq = (t & 1) ? PD - 1 : 0;
-            ex = xq - NG;
-        }
+    const int q = qx + NG;
+    int xq = -1, xlb = 0, ex = 0;
+    if (t < NXT2) {
+        xlb = t >> 1;
+        xq = (t & 1) ? PD - 1 : 0;
+        ex = xq - NG;
     }
-    const bool xI = qx >= 0 && qx < NB;
-    const bool yI = NDIM == 2 || (qy >= 0 && qy < NB);
-    const bool inI = lane && xI && yI;
+    const bool inI = lane && qx >= 0 && qx < NB;
 
     Phys<T, MIXED> ph;
     ph.gamma = (T)a.gamma;
@@ -167,23 +79,20 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
     const T *Uin = (const T *)a.Uin;
     T *Uout = (T *)a.Uout;
     T *fbuf = (T *)a.fbuf;
-    const int lim = a.limiter;
 
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-        // 3-D: one block per workgroup, so the block and everything derived
-        // from it are wave-uniform (scalar registers)
-        const int li = NDIM == 3 ? item : item * BPW + lb;
-        const bool has = NDIM == 3 ? (item < a.nleaves) : (lane && li < a.nleaves);
-        const int slot = NDIM == 3 ? a.leaves[item] : (has ? a.leaves[li] : 0);
+        const int li = item * BPW + lb;
+        const bool has = lane && li < a.nleaves;
+        const int slot = has ? a.leaves[li] : 0;
         const int lix = item * BPW + xlb;
         const bool xhas = xq >= 0 && lix < a.nleaves;
         const int xslot = xhas ? a.leaves[lix] : 0;
         const BlockRec br = a.blk[slot];
         const map_dt rec = a.dt[br.sim];
         const double *dxp = a.lvl_dx + ((size_t)br.sim * (MAXL + 1) + br.level) * 3;
-        T dtdx[NDIM], hdt[NDIM], i2d[NDIM];
+        T dtdx[2], hdt[2], i2d[2];
 #pragma unroll
-        for (int d = 0; d < NDIM; d++) {
+        for (int d = 0; d < 2; d++) {
             double r = rec.dt / dxp[d];
             dtdx[d] = (T)r;
             hdt[d] = (T)(0.5 * r);
@@ -193,15 +102,11 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         const T eta = (T)a.eta;
         T *ob = Uout + (size_t)slot * NV * P;
 
-        auto set_src = [&](size_t *tab, int stride, int sl, int cx, int cy) {
-            const int zr[5] = {-2, -1, 0, NB, NB + 1};
+        auto set_src = [&](size_t *tab, int stride, int sl, int cx) {
+            const int yr[5] = {-2, -1, 0, NB, NB + 1};
 #pragma unroll
-            for (int r = 0; r < 5; r++) {
-                if constexpr (NDIM == 3)
-                    tab[r * stride] = cell_src<3>(a.desc, sl, cx, cy, zr[r]);
-                else
-                    tab[r * stride] = cell_src<2>(a.desc, sl, cx, zr[r], 0);
-            }
+            for (int r = 0; r < 5; r++)
+                tab[r * stride] = cell_src<2>(a.desc, sl, cx, yr[r], 0);
         };
         // k is the same for the whole workgroup: the region choice is uniform
         auto src_of = [&](const size_t *tab, int stride, int k) -> const T * {
@@ -212,13 +117,13 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
             return Uin + tab[(k - NB + 3) * stride];
         };
         if (has)
-            set_src(gcol + t, SG<NDIM>::NT, slot, qx, qy);
+            set_src(gcol + t, NT2, slot, qx);
         if (xhas)
-            set_src(gxc + t, NXT, xslot, ex, ey);
+            set_src(gxc + t, NXT2, xslot, ex);
 
         auto load = [&](T(&dst)[NV], int k) {
             if (has) {
-                const T *p = src_of(gcol + t, SG<NDIM>::NT, k);
+                const T *p = src_of(gcol + t, NT2, k);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     dst[v] = p[v * P];
@@ -232,23 +137,31 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
         };
         auto load_x = [&](T(&dst)[NV], int k) {
             if (xhas) {
-                const T *p = src_of(gxc + t, NXT, k);
+                const T *p = src_of(gxc + t, NXT2, k);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     dst[v] = p[v * P];
             }
         };
 
-        T um[NV], u0[NV], up[NV], upp[NV], xc[NV];
-        load(um, -2);
+        T u0[NV], up[NV], upp[NV], xc[NV];
+        {
+            // row -2 of the own column: read back as the k-1 row at k = -1
+            T um[NV];
+            load(um, -2);
+            if (lane) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    su[(lb * NV + v) * XS + q] = um[v];
+            }
+        }
         load(u0, -1);
         load(up, 0);
         load_x(xc, -1);
-        // carried to the next plane: Wc = u - (in-plane flux differences)
-        // + dt (sources + in-plane resistive terms), the flux of the face
-        // k-1/2 (the march-axis difference is taken as a difference, so a
-        // uniform state stays exactly uniform), the left state of the face
-        // k+1/2, and eta J of the two previous planes
+        // carried to the next row: Wc = u - (x flux difference) + dt (sources
+        // + x resistive terms), the flux of the face k-1/2 (the y difference
+        // is taken as a difference, so a uniform state stays exactly
+        // uniform), the left state of the face k+1/2, eta J of two rows
         T Lm_prev[NV], Wc[NV], fm_prev[NV];
         T pLm_prev = T(1);
         T jm1[3], jm2[3];
@@ -266,16 +179,19 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
 
         for (int k = -1; k <= NB; ++k) {
             const bool kI = k >= 0 && k < NB;
-            // ---- (A) publish plane k (own column and the load-only cell)
+            T *const sc = su + ((k + 2) & 1) * SUB;        // row k
+            const T *const sm = su + ((k + 1) & 1) * SUB;  // row k-1
+            auto um = [&](int v) { return sm[(lb * NV + v) * XS + q]; };
+            // ---- (A) publish row k (own column and the load-only cell)
             if (lane) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    su[(lb * NV + v) * XS + q] = u0[v];
+                    sc[(lb * NV + v) * XS + q] = u0[v];
             }
             if (xhas) {
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    su[(xlb * NV + v) * XS + xq] = xc[v];
+                    sc[(xlb * NV + v) * XS + xq] = xc[v];
             }
             if (k + 2 <= NB + 1)
                 load(upp, k + 2);
@@ -283,22 +199,20 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                 load_x(xc, k + 1);
             __syncthreads();
 
-            T Lin[DIN][NV], pLin[DIN], Lm[NV], Rm[NV];
+            T Lin[NV], pLin = T(1), Lm[NV], Rm[NV];
             T pLm = T(1), pRm = T(1);
             T src[4] = {T(0), T(0), T(0), T(0)};
             T jc[3] = {T(0), T(0), T(0)};
-            // planes -1 and NB only feed the faces between planes: interior columns
+            // rows -1 and NB only feed the faces between rows: interior columns
             const bool work = lane && (kI || inI);
             if (work) {
                 // slopes from the old-time differences (limiter1)
-                T dl[NDIM][NV];
+                T dl[2][NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    const T *row = su + (lb * NV + v) * XS;
-                    dl[0][v] = limiter(lim, u0[v] - row[q - 1], row[q + 1] - u0[v]);
-                    if constexpr (NDIM == 3)
-                        dl[1][v] = limiter(lim, u0[v] - row[q - SY], row[q + SY] - u0[v]);
-                    dl[MD][v] = limiter(lim, u0[v] - um[v], up[v] - u0[v]);
+                    const T *row = sc + (lb * NV + v) * XS;
+                    dl[0][v] = limiter<LIM>(u0[v] - row[q - 1], row[q + 1] - u0[v]);
+                    dl[1][v] = limiter<LIM>(u0[v] - um(v), up[v] - u0[v]);
                 }
                 // half-step predictor u~ = u - dt/(2dx) sum_d [f(u + D/2) - f(u - D/2)],
                 // evaluated optimistically; if any face state of the cell has
@@ -330,11 +244,9 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                 };
                 pred(std::integral_constant<int, 0>{});
                 pred(std::integral_constant<int, 1>{});
-                if constexpr (NDIM == 3)
-                    pred(std::integral_constant<int, 2>{});
                 if (!ok) {
 #pragma unroll
-                    for (int d = 0; d < NDIM; d++)
+                    for (int d = 0; d < 2; d++)
 #pragma unroll
                         for (int v = 0; v < NV; v++)
                             dl[d][v] = T(0);
@@ -350,9 +262,9 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                     ut[v] = u0[v] - acc[v];
                 // face states with the old-time slopes (limiter2); a state with
                 // rho <= 0 or p <= 0 is replaced by the cell's u~
-                const int qc[3] = {qx, NDIM == 3 ? qy : k, k};
+                const int qc[2] = {qx, k};
 #pragma unroll
-                for (int d = 0; d < NDIM; d++) {
+                for (int d = 0; d < 2; d++) {
                     T L[NV], R[NV];
                     Prim<T> wl, wr;
 #pragma unroll
@@ -362,11 +274,8 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                     }
                     prim_of(ph, L, wl);
                     prim_of(ph, R, wr);
-                    bool others = true;
-#pragma unroll
-                    for (int e = 0; e < NDIM; e++)
-                        if (e != d)
-                            others = others && qc[e] >= 0 && qc[e] < NB;
+                    // count a replaced state once, for faces of interior cells
+                    const bool others = qc[1 - d] >= 0 && qc[1 - d] < NB;
                     if (!admissible_w(L, wl)) {
 #pragma unroll
                         for (int v = 0; v < NV; v++)
@@ -383,14 +292,14 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                         if (has && others && qc[d] >= 0)
                             atomicAdd(&a.cnt[1], 1ull);
                     }
-                    if (d < DIN) {
+                    if (d == 0) {
 #pragma unroll
                         for (int v = 0; v < NV; v++) {
-                            srf[((lb * DIN + d) * NV + v) * XS + q] = R[v];
-                            Lin[d < DIN ? d : 0][v] = L[v];
+                            srf[(lb * NV + v) * XS + q] = R[v];
+                            Lin[v] = L[v];
                         }
-                        spr[(lb * DIN + d) * XS + q] = wr.p;
-                        pLin[d < DIN ? d : 0] = wl.p;
+                        spr[lb * XS + q] = wr.p;
+                        pLin = wl.p;
                     } else {
 #pragma unroll
                         for (int v = 0; v < NV; v++) {
@@ -403,188 +312,116 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                 }
                 // EGLM sources from central differences of u^n
                 if (a.eglm && inI && kI) {
-                    const T *bx = su + (lb * NV + BX) * XS, *by = su + (lb * NV + BY) * XS;
-                    const T *ps = su + (lb * NV + PSI) * XS;
+                    const T *bx = sc + (lb * NV + BX) * XS;
+                    const T *ps = sc + (lb * NV + PSI) * XS;
                     T divb = (bx[q + 1] - bx[q - 1]) * i2d[0];
                     T bgp = u0[BX] * ((ps[q + 1] - ps[q - 1]) * i2d[0]);
-                    if constexpr (NDIM == 3) {
-                        divb += (by[q + SY] - by[q - SY]) * i2d[1];
-                        bgp += u0[BY] * ((ps[q + SY] - ps[q - SY]) * i2d[1]);
-                    }
-                    divb += (up[BX + MD] - um[BX + MD]) * i2d[MD];
-                    bgp += u0[BX + MD] * ((up[PSI] - um[PSI]) * i2d[MD]);
+                    divb += (up[BY] - um(BY)) * i2d[1];
+                    bgp += u0[BY] * ((up[PSI] - um(PSI)) * i2d[1]);
                     src[0] = divb * u0[BX];
                     src[1] = divb * u0[BY];
                     src[2] = divb * u0[BZ];
                     src[3] = bgp;
                 }
-                // resistivity: eta J and eta (J x B) on this plane
+                // resistivity: eta J and eta (J x B) on this row
                 if constexpr (RESIST) {
-                    const T *bx = su + (lb * NV + BX) * XS, *by = su + (lb * NV + BY) * XS;
-                    const T *bz = su + (lb * NV + BZ) * XS;
-                    T jx, jy, jz;
-                    if constexpr (NDIM == 3) {
-                        T dyBz = (bz[q + SY] - bz[q - SY]) * i2d[1];
-                        T dzBy = (up[BY] - um[BY]) * i2d[2];
-                        T dzBx = (up[BX] - um[BX]) * i2d[2];
-                        T dxBz = (bz[q + 1] - bz[q - 1]) * i2d[0];
-                        T dxBy = (by[q + 1] - by[q - 1]) * i2d[0];
-                        T dyBx = (bx[q + SY] - bx[q - SY]) * i2d[1];
-                        jx = dyBz - dzBy;
-                        jy = dzBx - dxBz;
-                        jz = dxBy - dyBx;
-                    } else {
-                        T dyBz = (up[BZ] - um[BZ]) * i2d[1];
-                        T dxBz = (bz[q + 1] - bz[q - 1]) * i2d[0];
-                        T dxBy = (by[q + 1] - by[q - 1]) * i2d[0];
-                        T dyBx = (up[BX] - um[BX]) * i2d[1];
-                        jx = dyBz;
-                        jy = -dxBz;
-                        jz = dxBy - dyBx;
-                    }
-                    T ejx = eta * jx, ejy = eta * jy, ejz = eta * jz;
-                    T qx_ = eta * (jz * u0[BY] - jy * u0[BZ]);
-                    T qy_ = eta * (jx * u0[BZ] - jz * u0[BX]);
-                    T qz_ = eta * (jy * u0[BX] - jx * u0[BY]);
+                    const T *by = sc + (lb * NV + BY) * XS, *bz = sc + (lb * NV + BZ) * XS;
+                    const T dyBz = (up[BZ] - um(BZ)) * i2d[1];
+                    const T dxBz = (bz[q + 1] - bz[q - 1]) * i2d[0];
+                    const T dxBy = (by[q + 1] - by[q - 1]) * i2d[0];
+                    const T dyBx = (up[BX] - um(BX)) * i2d[1];
+                    const T jx = dyBz, jy = -dxBz, jz = dxBy - dyBx;
+                    const T ejx = eta * jx, ejy = eta * jy, ejz = eta * jz;
+                    const T qx_ = eta * (jz * u0[BY] - jy * u0[BZ]);
+                    const T qy_ = eta * (jx * u0[BZ] - jz * u0[BX]);
                     T *J = sj + lb * 5 * XS;
                     J[0 * XS + q] = ejx;
                     J[1 * XS + q] = ejy;
                     J[2 * XS + q] = ejz;
                     J[3 * XS + q] = qx_;
                     J[4 * XS + q] = qy_;
-                    if constexpr (NDIM == 3) {
-                        jc[0] = ejx;
-                        jc[1] = ejy;
-                        jc[2] = qz_;
-                    } else {
-                        jc[0] = ejx;
-                        jc[1] = ejz;
-                        jc[2] = qy_;
-                    }
+                    jc[0] = ejx;
+                    jc[1] = ejz;
+                    jc[2] = qy_;
                 }
             }
             __syncthreads();  // (B) right face states, their pressures and eta J published
 
-            // ---- fluxes of the in-plane faces of plane k and of the face k-1/2
-            T fin[DIN][NV];
-            bool dof[DIN];
-            T rin[4] = {T(0), T(0), T(0), T(0)};
-            dof[0] = kI && lane && qx >= -1 && qx < NB && yI;
-            if constexpr (NDIM == 3)
-                dof[DIN - 1] = kI && lane && qy >= -1 && qy < NB && xI;
-            if (dof[0]) {
+            // ---- fluxes of the x faces of row k and of the face k-1/2
+            T fin[NV];
+            T rin[3] = {T(0), T(0), T(0)};
+            const bool dof = kI && lane && qx >= -1 && qx < NB;
+            if (dof) {
                 T R[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    R[v] = srf[((lb * DIN + 0) * NV + v) * XS + q + 1];
-                rusanov_p<0>(Lin[0], pLin[0], R, spr[(lb * DIN + 0) * XS + q + 1], gam, ch, ch2,
-                             fin[0]);
-            }
-            if constexpr (NDIM == 3) {
-                if (dof[1]) {
-                    T R[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        R[v] = srf[((lb * DIN + 1) * NV + v) * XS + q + SY];
-                    rusanov_p<1>(Lin[1], pLin[1], R, spr[(lb * DIN + 1) * XS + q + SY], gam, ch,
-                                 ch2, fin[1]);
-                }
+                    R[v] = srf[(lb * NV + v) * XS + q + 1];
+                rusanov_p<0>(Lin, pLin, R, spr[lb * XS + q + 1], gam, ch, ch2, fin);
             }
             if constexpr (RESIST) {
                 if (inI && kI) {
                     const T *J = sj + lb * 5 * XS;
-                    const T *J0 = J, *J1 = J + XS, *J2 = J + 2 * XS, *Q0 = J + 3 * XS, *Q1 = J + 4 * XS;
-                    if constexpr (NDIM == 3) {
-                        rin[0] = -((J2[q + SY] - J2[q - SY]) * i2d[1]);
-                        rin[1] = (J2[q + 1] - J2[q - 1]) * i2d[0];
-                        rin[2] = (J0[q + SY] - J0[q - SY]) * i2d[1] - (J1[q + 1] - J1[q - 1]) * i2d[0];
-                        rin[3] = (Q0[q + 1] - Q0[q - 1]) * i2d[0] + (Q1[q + SY] - Q1[q - SY]) * i2d[1];
-                    } else {
-                        rin[0] = (J2[q + 1] - J2[q - 1]) * i2d[0];
-                        rin[1] = (J1[q + 1] - J1[q - 1]) * i2d[0];
-                        rin[2] = (Q0[q + 1] - Q0[q - 1]) * i2d[0];
-                    }
+                    const T *J1 = J + XS, *J2 = J + 2 * XS, *Q0 = J + 3 * XS;
+                    rin[0] = (J2[q + 1] - J2[q - 1]) * i2d[0];
+                    rin[1] = (J1[q + 1] - J1[q - 1]) * i2d[0];
+                    rin[2] = (Q0[q + 1] - Q0[q - 1]) * i2d[0];
                 }
             }
             const bool dom = inI && k >= 0;
             T fmc[NV];
             if (dom)
-                rusanov_p<MD>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
+                rusanov_p<1>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
             __syncthreads();  // (C) all reads of the right face states done
+            if (dof) {
 #pragma unroll
-            for (int d = 0; d < DIN; d++)
-                if (dof[d]) {
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        srf[((lb * DIN + d) * NV + v) * XS + q] = fin[d][v];
-                }
+                for (int v = 0; v < NV; v++)
+                    srf[(lb * NV + v) * XS + q] = fin[v];
+            }
             // fluxes of block faces shared with another level (reflux)
             if (has) {
-#pragma unroll
-                for (int d = 0; d < DIN; d++) {
-                    if (!dof[d])
-                        continue;
-                    const int qd = d == 0 ? qx : qy;
-                    const int side = qd == -1 ? 0 : (qd == NB - 1 ? 1 : -1);
-                    if (side < 0)
-                        continue;
-                    const int fb = a.fbidx[(size_t)slot * 6 + 2 * d + side];
-                    if (fb < 0)
-                        continue;
-                    int tt;
-                    if constexpr (NDIM == 3)
-                        tt = (d == 0 ? qy : qx) + NB * k;
-                    else
-                        tt = k;
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        fbuf[((size_t)fb * NV + v) * FC + tt] = fin[d][v];
-                }
-                if (dom && (k == 0 || k == NB)) {
-                    const int fb = a.fbidx[(size_t)slot * 6 + 2 * MD + (k == NB ? 1 : 0)];
+                if (dof && (qx == -1 || qx == NB - 1)) {
+                    const int fb = a.fbidx[(size_t)slot * 6 + (qx == -1 ? 0 : 1)];
                     if (fb >= 0) {
-                        const int tt = NDIM == 3 ? qx + NB * qy : qx;
 #pragma unroll
                         for (int v = 0; v < NV; v++)
-                            fbuf[((size_t)fb * NV + v) * FC + tt] = fmc[v];
+                            fbuf[((size_t)fb * NV + v) * FC + k] = fin[v];
+                    }
+                }
+                if (dom && (k == 0 || k == NB)) {
+                    const int fb = a.fbidx[(size_t)slot * 6 + 2 + (k == NB ? 1 : 0)];
+                    if (fb >= 0) {
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            fbuf[((size_t)fb * NV + v) * FC + qx] = fmc[v];
                     }
                 }
             }
-            __syncthreads();  // (D) in-plane face fluxes published
+            __syncthreads();  // (D) x face fluxes published
 
-            // ---- finalise plane k-1 with the face k-1/2: march-axis flux
-            //      difference, march-axis resistive terms, psi damping (MHD-5
-            //      integrated exactly)
+            // ---- finalise row k-1 with the face k-1/2: y flux difference,
+            //      y resistive terms, psi damping (MHD-5 integrated exactly)
             if (dom && k >= 1 && has) {
                 T o[NV];
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    o[v] = Wc[v] - dtdx[MD] * (fmc[v] - fm_prev[v]);
+                    o[v] = Wc[v] - dtdx[1] * (fmc[v] - fm_prev[v]);
                 if constexpr (RESIST) {
-                    if constexpr (NDIM == 3) {
-                        o[BX] = o[BX] + dt * ((jc[1] - jm2[1]) * i2d[2]);
-                        o[BY] = o[BY] - dt * ((jc[0] - jm2[0]) * i2d[2]);
-                        o[EN] = o[EN] + dt * ((jc[2] - jm2[2]) * i2d[2]);
-                    } else {
-                        o[BX] = o[BX] - dt * ((jc[1] - jm2[1]) * i2d[1]);
-                        o[BZ] = o[BZ] + dt * ((jc[0] - jm2[0]) * i2d[1]);
-                        o[EN] = o[EN] + dt * ((jc[2] - jm2[2]) * i2d[1]);
-                    }
+                    o[BX] = o[BX] - dt * ((jc[1] - jm2[1]) * i2d[1]);
+                    o[BZ] = o[BZ] + dt * ((jc[0] - jm2[0]) * i2d[1]);
+                    o[EN] = o[EN] + dt * ((jc[2] - jm2[2]) * i2d[1]);
                 }
                 o[PSI] = o[PSI] * damp;
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ob[v * P + (k - 1 + NG) * XS + q] = o[v];
             }
-            // ---- start plane k: in-plane flux differences, EGLM sources and
-            //      in-plane resistive terms
+            // ---- start row k: x flux difference, EGLM sources and x
+            //      resistive terms
             if (inI && kI) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    T acc = dtdx[0] * (fin[0][v] - srf[((lb * DIN + 0) * NV + v) * XS + q - 1]);
-                    if constexpr (NDIM == 3)
-                        acc += dtdx[1] * (fin[1][v] - srf[((lb * DIN + 1) * NV + v) * XS + q - SY]);
-                    Wc[v] = u0[v] - acc;
+                    const T acc = dtdx[0] * (fin[v] - srf[(lb * NV + v) * XS + q - 1]);
+                    Wc[v] = sc[(lb * NV + v) * XS + q] - acc;
                 }
                 if (a.eglm) {
                     Wc[MX] = Wc[MX] - dt * src[0];
@@ -593,16 +430,9 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
                     Wc[EN] = Wc[EN] - dt * src[3];
                 }
                 if constexpr (RESIST) {
-                    if constexpr (NDIM == 3) {
-                        Wc[BX] = Wc[BX] + dt * rin[0];
-                        Wc[BY] = Wc[BY] + dt * rin[1];
-                        Wc[BZ] = Wc[BZ] + dt * rin[2];
-                        Wc[EN] = Wc[EN] + dt * rin[3];
-                    } else {
-                        Wc[BY] = Wc[BY] + dt * rin[0];
-                        Wc[BZ] = Wc[BZ] - dt * rin[1];
-                        Wc[EN] = Wc[EN] + dt * rin[2];
-                    }
+                    Wc[BY] = Wc[BY] + dt * rin[0];
+                    Wc[BZ] = Wc[BZ] - dt * rin[1];
+                    Wc[EN] = Wc[EN] + dt * rin[2];
                 }
             }
             // ---- shift the march-axis registers
@@ -610,7 +440,6 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
             for (int v = 0; v < NV; v++) {
                 fm_prev[v] = dom ? fmc[v] : T(0);
                 Lm_prev[v] = work ? Lm[v] : T(0);
-                um[v] = u0[v];
                 u0[v] = up[v];
                 up[v] = upp[v];
             }
@@ -625,38 +454,43 @@ __global__ void __launch_bounds__(SG<NDIM>::NT) k_step_lf(StepArgs a)
     }
 }
 
-template <int NDIM, typename T, bool MIXED, bool RESIST>
-static hipError_t launch_one(const StepArgs &a, int grid, hipStream_t s)
+template <typename T, bool MIXED, bool RESIST, int LIM>
+static hipError_t launch2(const StepArgs &a, int grid, hipStream_t s)
+{
+    const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
+    hipLaunchKernelGGL((k_step_lf2<T, MIXED, RESIST, LIM>), dim3(g), dim3(NT2), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, bool MIXED, bool RESIST>
+static hipError_t launch2_lim(const StepArgs &a, int grid, hipStream_t s)
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
-    hipLaunchKernelGGL((k_step_lf<NDIM, T, MIXED, RESIST>), dim3(g), dim3(SG<NDIM>::NT), 0, s, a);
-    return hipGetLastError();
+    if (a.limiter == MAP_MINMOD)
+        return launch2<T, MIXED, RESIST, MAP_MINMOD>(a, grid, s);
+    if (a.limiter == MAP_VANLEER)
+        return launch2<T, MIXED, RESIST, MAP_VANLEER>(a, grid, s);
+    return launch2<T, MIXED, RESIST, MAP_PAPER_PHI>(a, grid, s);
 }
 
 int step_blocks_per_group(int ndim, int scheme)
 {
-    if (scheme == MAP_MMC)
+    if (scheme == MAP_MMC || ndim == 3)
         return 1;
-    return ndim == 3 ? SG<3>::BPW : SG<2>::BPW;
+    return BPW2;
 }
 
 hipError_t launch_step_lf(int ndim, bool fp64, bool resist, const StepArgs &a, int grid,
                           hipStream_t s)
 {
-    if (ndim == 2) {
-        if (fp64)
-            return resist ? launch_one<2, double, false, true>(a, grid, s)
-                          : launch_one<2, double, false, false>(a, grid, s);
-        return resist ? launch_one<2, float, true, true>(a, grid, s)
-                      : launch_one<2, float, true, false>(a, grid, s);
-    }
+    if (ndim == 3)
+        return launch_step_lf3(fp64, resist, a, grid, s);
     if (fp64)
-        return resist ? launch_one<3, double, false, true>(a, grid, s)
-                      : launch_one<3, double, false, false>(a, grid, s);
-    return resist ? launch_one<3, float, true, true>(a, grid, s)
-                  : launch_one<3, float, true, false>(a, grid, s);
+        return resist ? launch2_lim<double, false, true>(a, grid, s)
+                      : launch2_lim<double, false, false>(a, grid, s);
+    return resist ? launch2_lim<float, true, true>(a, grid, s)
+                  : launch2_lim<float, true, false>(a, grid, s);
 }
 
 }  // namespace mapk

@@ -26,7 +26,7 @@ constexpr int NT = 256;
 __device__ __forceinline__ int pidx(int x, int y) { return (y + NG) * PD + (x + NG); }
 }  // namespace
 
-template <typename T, bool MIXED>
+template <typename T, bool MIXED, int LIM>
 __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
 {
     __shared__ T sfp[NV * T2], sfm[NV * T2];
@@ -41,7 +41,6 @@ __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
     const T *Uin = (const T *)a.Uin;
     T *Uout = (T *)a.Uout;
     T *fbuf = (T *)a.fbuf;
-    const int lim = a.limiter;
     const int t = threadIdx.x;
 
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
@@ -172,7 +171,7 @@ __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
                     T gp_p = TP[ce + se] - FP[c];
                     T gm_p = FM[c + s] - TM[ce];
                     T gm_pp = FM[c + 2 * s] - TM[ce + se];
-                    fh[v] = h + T(0.5) * (limiter(lim, gp_m, gp_p) - limiter(lim, gm_pp, gm_p));
+                    fh[v] = h + T(0.5) * (limiter<LIM>(gp_m, gp_p) - limiter<LIM>(gm_pp, gm_p));
                     sfh[v * F2 + f] = fh[v];
                 }
                 // block faces shared with another level (reflux)
@@ -234,6 +233,23 @@ __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
     }
 }
 
+template <typename T, bool MIXED, int LIM>
+static void launch_mmc(const StepArgs &a, int g, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_step_mmc2<T, MIXED, LIM>), dim3(g), dim3(NT), 0, s, a);
+}
+
+template <typename T, bool MIXED>
+static void launch_mmc_lim(const StepArgs &a, int g, hipStream_t s)
+{
+    if (a.limiter == MAP_MINMOD)
+        launch_mmc<T, MIXED, MAP_MINMOD>(a, g, s);
+    else if (a.limiter == MAP_VANLEER)
+        launch_mmc<T, MIXED, MAP_VANLEER>(a, g, s);
+    else
+        launch_mmc<T, MIXED, MAP_PAPER_PHI>(a, g, s);
+}
+
 hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double, int grid, hipStream_t s)
 {
     if (ndim != 2)
@@ -242,9 +258,9 @@ hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double, int g
         return hipSuccess;
     int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
     if (fp64)
-        hipLaunchKernelGGL((k_step_mmc2<double, false>), dim3(g), dim3(NT), 0, s, a);
+        launch_mmc_lim<double, false>(a, g, s);
     else
-        hipLaunchKernelGGL((k_step_mmc2<float, true>), dim3(g), dim3(NT), 0, s, a);
+        launch_mmc_lim<float, true>(a, g, s);
     return hipGetLastError();
 }
 

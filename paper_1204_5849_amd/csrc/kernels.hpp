@@ -86,6 +86,7 @@ struct TotalsArgs {
 // launchers (defined in the .hip files); return hipError_t of the launch
 hipError_t launch_step_lf(int ndim, bool fp64, bool resist, const StepArgs &a, int grid,
                           hipStream_t s);
+hipError_t launch_step_lf3(bool fp64, bool resist, const StepArgs &a, int grid, hipStream_t s);
 hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double alpha_unused, int grid,
                            hipStream_t s);
 int step_blocks_per_group(int ndim, int scheme);

@@ -55,19 +55,21 @@ __device__ __forceinline__ float lim_minmod<float>(float a, float b)
     return __builtin_amdgcn_fmed3f(a, b, 0.0f);
 }
 
-// limiter selected at run time (uniform across the launch):
-// minmod, van Leer (ab + |ab|)/(a + b), or the literal flux limiter of
-// Sec. 3.1 in ratio-free form phi(a/b) b
-template <typename T>
-__device__ __forceinline__ T limiter(int kind, T a, T b)
+// slope / flux limiter, chosen at compile time (kernels are instantiated
+// per limiter so that no per-call dispatch sits in the cell loop): minmod,
+// van Leer (ab + |ab|)/(a + b), or the literal flux limiter of Sec. 3.1 in
+// ratio-free form phi(a/b) b
+template <int KIND, typename T>
+__device__ __forceinline__ T limiter(T a, T b)
 {
-    if (kind == MAP_MINMOD)
+    if constexpr (KIND == MAP_MINMOD) {
         return lim_minmod(a, b);
-    if (kind == MAP_VANLEER) {
+    } else if constexpr (KIND == MAP_VANLEER) {
         T ab = a * b;
         return ab <= T(0) ? T(0) : Num<T>::div(ab + fabs(ab), a + b);
+    } else {
+        return fabs(a) <= fabs(b) ? a : b;
     }
-    return fabs(a) <= fabs(b) ? a : b;
 }
 
 template <typename T, bool MIXED>
@@ -189,43 +191,58 @@ __device__ __forceinline__ bool admissible_w(const T u[NV], const Prim<T> &w)
     return u[RHO] > T(0) && w.p > T(0);
 }
 
-// EGLM flux along D from a state and its primitives
-template <int D, typename T>
-__device__ __forceinline__ void flux_w(const T u[NV], const Prim<T> &w, T ch2, T f[NV])
+// EGLM flux along dimension d from a state and its primitives.  d may differ
+// between lanes (a wave that serves faces of several orientations); with a
+// constant d the selects fold away, so every caller forms the same
+// arithmetic and a flux does not depend on which lane evaluated it.
+template <typename T>
+__device__ __forceinline__ void flux_sel(const T u[NV], const Prim<T> &w, int d, T ch2, T f[NV])
 {
-    const T v[3] = {w.vx, w.vy, w.vz};
-    const T B[3] = {u[BX], u[BY], u[BZ]};
     const T me = T(0.5) * w.bb;
     const T pt = w.p + me;
-    const T vd = v[D], Bd = B[D];
-    const T vb = v[0] * B[0] + v[1] * B[1] + v[2] * B[2];
-    f[RHO] = u[MX + D];
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-        f[MX + j] = u[MX + j] * vd - B[j] * Bd;
-    f[MX + D] = f[MX + D] + pt;
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-        f[BX + j] = B[j] * vd - Bd * v[j];
-    f[BX + D] = u[PSI];
+    const T vd = d == 0 ? w.vx : (d == 1 ? w.vy : w.vz);
+    const T Bd = d == 0 ? u[BX] : (d == 1 ? u[BY] : u[BZ]);
+    const T vb = w.vx * u[BX] + w.vy * u[BY] + w.vz * u[BZ];
+    f[RHO] = d == 0 ? u[MX] : (d == 1 ? u[MY] : u[MZ]);
+    f[MX] = u[MX] * vd - u[BX] * Bd;
+    f[MY] = u[MY] * vd - u[BY] * Bd;
+    f[MZ] = u[MZ] * vd - u[BZ] * Bd;
+    f[MX] = d == 0 ? f[MX] + pt : f[MX];
+    f[MY] = d == 1 ? f[MY] + pt : f[MY];
+    f[MZ] = d == 2 ? f[MZ] + pt : f[MZ];
+    f[BX] = d == 0 ? u[PSI] : u[BX] * vd - Bd * w.vx;
+    f[BY] = d == 1 ? u[PSI] : u[BY] * vd - Bd * w.vy;
+    f[BZ] = d == 2 ? u[PSI] : u[BZ] * vd - Bd * w.vz;
     f[EN] = (u[EN] + pt) * vd - Bd * vb;
     f[PSI] = ch2 * Bd;
 }
 
-// |v_D| + c_f,D from a state and its primitives
 template <int D, typename T>
-__device__ __forceinline__ T speed_w(const T u[NV], const Prim<T> &w, T gamma)
+__device__ __forceinline__ void flux_w(const T u[NV], const Prim<T> &w, T ch2, T f[NV])
+{
+    flux_sel(u, w, D, ch2, f);
+}
+
+// |v_d| + c_f,d from a state and its primitives (d as in flux_sel)
+template <typename T>
+__device__ __forceinline__ T speed_sel(const T u[NV], const Prim<T> &w, int d, T gamma)
 {
     const T a2 = gamma * w.p * w.ir;
     const T b2 = w.bb * w.ir;
     const T s = a2 + b2;
-    const T Bd = u[BX + D];
+    const T Bd = d == 0 ? u[BX] : (d == 1 ? u[BY] : u[BZ]);
     T disc = s * s - T(4) * a2 * (Bd * Bd) * w.ir;
     disc = disc < T(0) ? T(0) : disc;
     T cf2 = T(0.5) * (s + Num<T>::sqrt_(disc));
     cf2 = cf2 < T(0) ? T(0) : cf2;
-    const T vd = D == 0 ? w.vx : (D == 1 ? w.vy : w.vz);
+    const T vd = d == 0 ? w.vx : (d == 1 ? w.vy : w.vz);
     return fabs(vd) + Num<T>::sqrt_(cf2);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ T speed_w(const T u[NV], const Prim<T> &w, T gamma)
+{
+    return speed_sel(u, w, D, gamma);
 }
 
 }  // namespace mapk
