@@ -83,7 +83,8 @@ ALU_PEAK_TFLOPS = 78.6
 def step_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_step_lf.hip", "physics.hpp", "kernels.hpp", "map_internal.hpp"):
+    for f in ("k_step_lf.hip", "k_step_lf3.hip", "step_common.hpp", "tile.hpp", "physics.hpp",
+              "kernels.hpp", "map_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1204_5849_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -259,7 +260,8 @@ def main():
                    else "hipGraph, batched persistent", "grids": chosen},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "k_step_lf", "kernel_ms": t_step * 1e3,
+                     "kernel": "k_step_lf3" if wl.ndim == 3 else "k_step_lf2",
+                     "kernel_ms": t_step * 1e3,
                      "flops_per_cell_update": fpc, "algorithmic_bytes_per_launch": bytes_step,
                      "hbm_achieved_GBs": achieved, "hbm_peak_GBs": HBM_PEAK_GBS,
                      "hbm_frac": achieved / HBM_PEAK_GBS, "step_share_of_cycle": t_step * 1e3 / ms},

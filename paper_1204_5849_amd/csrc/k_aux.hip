@@ -11,6 +11,7 @@
 // memory-bound kernel).
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "sched.hpp"
 #include "tile.hpp"
 
 #pragma clang fp contract(off)
@@ -71,25 +72,6 @@ __device__ __forceinline__ void ghost_xyz(int g, int &x, int &y, int &z)
 }
 
 // ---- same-level copies and physical edges (descriptor src >= 0)
-// Work items of a persistent grid, mapped so that the workgroups on one XCD
-// (workgroups are dealt to the 8 XCDs round robin) walk one contiguous range
-// of the Morton-ordered list: neighbouring blocks then share that XCD's L2.
-__device__ __forceinline__ void xcd_range(int nitems, int &first, int &stride, int &end)
-{
-    const int G = gridDim.x;
-    if (G % 8 != 0 || G < 8) {
-        first = blockIdx.x;
-        stride = G;
-        end = nitems;
-        return;
-    }
-    const int x = blockIdx.x & 7, l = blockIdx.x >> 3, per = G >> 3;
-    const int chunk = (nitems + 7) / 8;
-    first = x * chunk + l;
-    stride = per;
-    end = min(nitems, (x + 1) * chunk);
-}
-
 template <int NDIM, typename T>
 __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
 {
@@ -161,7 +143,9 @@ __global__ void __launch_bounds__(NTA) k_prolong_ghosts(FillArgs a)
 {
     constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC;
     T *U = (T *)a.U;
-    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    int first, stride, end;
+    xcd_range(a.nitems, first, stride, end);  // siblings share the parent tile in L2
+    for (int item = first; item < end; item += stride) {
         const int slot = a.list[item];
         const int par = a.parent[slot];
         const int cpos = a.blk[slot].cpos;
@@ -210,9 +194,25 @@ __global__ void __launch_bounds__(NTA) k_prolong_blocks(FillArgs a)
 }
 
 // ---- restriction: parent cell = pairwise mean of its 2^d fine cells
+// ---- restriction: parent interior = mean of the 2^d child cells it covers
+// (Sec. 4.2, Sec. 4.3 step 1); one workgroup per parent.  The two cells of
+// an x pair are adjacent and 2-element aligned in the padded tile, so each
+// pair is one vector load; the sum is taken x pairs first, then y, then z.
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    using V = float2;
+};
+template <>
+struct Pair<double> {
+    using V = double2;
+};
+
 template <int NDIM, typename T>
 __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
 {
+    using V = typename Pair<T>::V;
     constexpr int P = FG<NDIM>::P, NI = FG<NDIM>::NI;
     T *U = (T *)a.U;
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
@@ -225,16 +225,20 @@ __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
             const T *cu = U + (size_t)a.children[(size_t)slot * 8 + cbit] * NV * P;
             const int lx = fx % NB, ly = fy % NB, lz = NDIM == 3 ? fz % NB : 0;
             const int c0 = lin<NDIM>(lx, ly, lz);
-            const int o[8] = {0, 1, PD, PD + 1, PD * PD, PD * PD + 1, PD * PD + PD, PD * PD + PD + 1};
 #pragma unroll
             for (int k = 0; k < NV; k++) {
                 const T *q = cu + (size_t)k * P + c0;
+                const V r0 = *reinterpret_cast<const V *>(q);
+                const V r1 = *reinterpret_cast<const V *>(q + PD);
                 T v;
-                if constexpr (NDIM == 2)
-                    v = ((q[o[0]] + q[o[1]]) + (q[o[2]] + q[o[3]])) * T(0.25);
-                else
-                    v = (((q[o[0]] + q[o[1]]) + (q[o[2]] + q[o[3]])) +
-                         ((q[o[4]] + q[o[5]]) + (q[o[6]] + q[o[7]]))) * T(0.125);
+                if constexpr (NDIM == 2) {
+                    v = ((r0.x + r0.y) + (r1.x + r1.y)) * T(0.25);
+                } else {
+                    const V r2 = *reinterpret_cast<const V *>(q + PD * PD);
+                    const V r3 = *reinterpret_cast<const V *>(q + PD * PD + PD);
+                    v = (((r0.x + r0.y) + (r1.x + r1.y)) + ((r2.x + r2.y) + (r3.x + r3.y))) *
+                        T(0.125);
+                }
                 ub[(size_t)k * P + lin<NDIM>(X, Y, Z)] = v;
             }
         }
@@ -320,17 +324,27 @@ __global__ void __launch_bounds__(NTA) k_cfl(CflArgs a)
                 nonfin++;
                 continue;
             }
-            double ir = 1.0 / u[RHO];
-            double ke = 0.5 * (u[MX] * (u[MX] * ir) + u[MY] * (u[MY] * ir) + u[MZ] * (u[MZ] * ir));
-            double me = 0.5 * (u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ]);
-            double pr = (a.gamma - 1.0) * (u[EN] - ke - me);
+            // primitives once per cell, then |v_d| + c_f,d for each d
+            const double ir = 1.0 / u[RHO];
+            const double vx = u[MX] * ir, vy = u[MY] * ir, vz = u[MZ] * ir;
+            const double ke = 0.5 * (u[MX] * vx + u[MY] * vy + u[MZ] * vz);
+            const double bb = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
+            const double pr = (a.gamma - 1.0) * (u[EN] - ke - 0.5 * bb);
             if (!(u[RHO] > 0.0) || !(pr > 0.0))
                 bad++;
-            double s = speed64<0>(a.gamma, u);
-            double s1 = speed64<1>(a.gamma, u);
+            const double a2 = a.gamma * pr * ir, sab = a2 + bb * ir;
+            auto fast = [&](double vd, double Bd) {
+                double disc = sab * sab - 4.0 * a2 * (Bd * Bd) * ir;
+                disc = disc < 0.0 ? 0.0 : disc;
+                double cf2 = 0.5 * (sab + sqrt(disc));
+                cf2 = cf2 < 0.0 ? 0.0 : cf2;
+                return fabs(vd) + sqrt(cf2);
+            };
+            double s = fast(vx, u[BX]);
+            const double s1 = fast(vy, u[BY]);
             s = s1 > s ? s1 : s;
             if constexpr (NDIM == 3) {
-                double s2 = speed64<2>(a.gamma, u);
+                const double s2 = fast(vz, u[BZ]);
                 s = s2 > s ? s2 : s;
             }
             m = s > m ? s : m;

@@ -25,6 +25,7 @@
 #include "kernels.hpp"
 #include "physics.hpp"
 #include "step_common.hpp"
+#include "sched.hpp"
 #include "tile.hpp"
 
 namespace mapk {
@@ -80,7 +81,11 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
     T *Uout = (T *)a.Uout;
     T *fbuf = (T *)a.fbuf;
 
-    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    // neighbouring blocks on one XCD, so that the ghost cells read from
+    // neighbours come from that XCD's L2
+    int first, stride, end;
+    xcd_range(a.nitems, first, stride, end);
+    for (int item = first; item < end; item += stride) {
         const int li = item * BPW + lb;
         const bool has = lane && li < a.nleaves;
         const int slot = has ? a.leaves[li] : 0;
@@ -102,19 +107,19 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
         const T eta = (T)a.eta;
         T *ob = Uout + (size_t)slot * NV * P;
 
-        auto set_src = [&](size_t *tab, int stride, int sl, int cx) {
+        auto set_src = [&](size_t *tab, int ts, int sl, int cx) {
             const int yr[5] = {-2, -1, 0, NB, NB + 1};
 #pragma unroll
             for (int r = 0; r < 5; r++)
-                tab[r * stride] = cell_src<2>(a.desc, sl, cx, yr[r], 0);
+                tab[r * ts] = cell_src<2>(a.desc, sl, cx, yr[r], 0);
         };
         // k is the same for the whole workgroup: the region choice is uniform
-        auto src_of = [&](const size_t *tab, int stride, int k) -> const T * {
+        auto src_of = [&](const size_t *tab, int ts, int k) -> const T * {
             if (k < 0)
-                return Uin + tab[(k + 2) * stride];
+                return Uin + tab[(k + 2) * ts];
             if (k < NB)
-                return Uin + tab[2 * stride] + k * XS;
-            return Uin + tab[(k - NB + 3) * stride];
+                return Uin + tab[2 * ts] + k * XS;
+            return Uin + tab[(k - NB + 3) * ts];
         };
         if (has)
             set_src(gcol + t, NT2, slot, qx);

@@ -31,6 +31,7 @@
 #include "kernels.hpp"
 #include "physics.hpp"
 #include "step_common.hpp"
+#include "sched.hpp"
 #include "tile.hpp"
 
 namespace mapk {
@@ -110,7 +111,11 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
     T *fbuf = (T *)a.fbuf;
     constexpr int FC = NB * NB;
 
-    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    // neighbouring blocks on one XCD, so that the ghost cells read from
+    // neighbours come from that XCD's L2
+    int first, stride, end;
+    xcd_range(a.nitems, first, stride, end);
+    for (int item = first; item < end; item += stride) {
         const int slot = a.leaves[item];
         const BlockRec br = a.blk[slot];
         const map_dt rec = a.dt[br.sim];

@@ -13,6 +13,7 @@
 // are reused by the first corrector dimension.
 #include "kernels.hpp"
 #include "physics.hpp"
+#include "sched.hpp"
 #include "tile.hpp"
 
 namespace mapk {
@@ -43,7 +44,11 @@ __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
     T *fbuf = (T *)a.fbuf;
     const int t = threadIdx.x;
 
-    for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    // neighbouring blocks on one XCD, so that the ghost cells read from
+    // neighbours come from that XCD's L2
+    int first, stride, end;
+    xcd_range(a.nitems, first, stride, end);
+    for (int item = first; item < end; item += stride) {
         if (item >= a.nleaves)
             break;
         const int slot = a.leaves[item];

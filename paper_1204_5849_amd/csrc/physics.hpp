@@ -146,27 +146,6 @@ struct Phys {
     }
 };
 
-// |v_d| + c_f,d evaluated in FP64 from a state of either precision (CFL pass)
-template <int D>
-__device__ __forceinline__ double speed64(double gamma, const double u[NV])
-{
-    double ir = 1.0 / u[RHO];
-    double vx = u[MX] * ir, vy = u[MY] * ir, vz = u[MZ] * ir;
-    double ke = 0.5 * (u[MX] * vx + u[MY] * vy + u[MZ] * vz);
-    double me = 0.5 * (u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ]);
-    double pr = (gamma - 1.0) * (u[EN] - ke - me);
-    double a2 = gamma * pr * ir;
-    double bb = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
-    double b2 = bb * ir;
-    double s = a2 + b2;
-    double disc = s * s - 4.0 * a2 * (u[BX + D] * u[BX + D]) * ir;
-    disc = disc < 0.0 ? 0.0 : disc;
-    double cf2 = 0.5 * (s + sqrt(disc));
-    cf2 = cf2 < 0.0 ? 0.0 : cf2;
-    double vd = D == 0 ? vx : (D == 1 ? vy : vz);
-    return fabs(vd) + sqrt(cf2);
-}
-
 // primitive quantities of one state, computed once and shared by the
 // admissibility test, the flux and the fast speed of that state
 template <typename T>

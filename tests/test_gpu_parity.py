@@ -312,3 +312,22 @@ def test_step_rejects_aliased_output(dev):
     N.map_step(s.ctx, s.U, out, s.dt, s.sp)
     s.sync()
     assert torch.isfinite(out).all()
+
+
+@pytest.mark.parametrize("name", ["harris", "blast"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_cycle_leaves_parents_restricted(dev, name, precision):
+    """After whole cycles (step, reflux, restriction) every parent equals,
+    bit for bit, what the restriction pass computes from the final leaves."""
+    if name == "harris":
+        w = W.harris3d(nbase=2, levels=3, precision=precision)
+    else:
+        w = W.blast3d(nbase=2, levels=2, precision=precision)
+    _say(f"parents restricted after cycles {name} {precision}")
+    s = _sim(w)
+    s.advance(3)
+    s.sync()
+    before = s.U.clone()
+    s.restrict()
+    s.sync()
+    assert torch.equal(s.U, before)
