@@ -51,6 +51,7 @@ enum { MAP_MINMOD = 0, MAP_VANLEER = 1, MAP_PAPER_PHI = 2 };
 enum { MAP_GLM_PAPER = 0, MAP_GLM_FASTSPEED = 1 };
 enum { MAP_BC_PERIODIC = 0, MAP_BC_OUTFLOW = 1 };
 enum { MAP_LAUNCH_BATCHED = 0, MAP_LAUNCH_PER_BLOCK = 1 };
+enum { MAP_EST_VAR = 0, MAP_EST_BMAG = 1 };
 
 /* Scheme parameters (Sec. 2 and 3).
  *   precision     MAP_FP64: state and arithmetic in FP64.  MAP_FP32_MIXED:
@@ -210,6 +211,65 @@ map_status map_set_launch(map_ctx *ctx, int mode, int grid_step, int grid_fill);
  * write the shadow state; U's interiors are not changed (ghost frames of
  * parents that feed prolongation are rewritten with the same values). */
 map_status map_autotune(map_ctx *ctx, void *U, int *chosen, void *stream);
+
+/* ---- regrid (Sec. 4.5) ------------------------------------------------ */
+
+/* Error estimator of Sec. 4.5, per cell,
+ *   (bias |D u| / (|u| + eps) + (1 - bias) |D2 u| / (|D u| + filt (|u| + eps)))
+ *     * ratio^(xi (L - 1)),
+ * |D u| = (sqrt 3 / 2) (sum_d (u_{+d} - u_{-d})^2)^(1/2),
+ * |D2 u| = (sum_d (u_{+d} - 2 u + u_{-d})^2)^(1/2),
+ * for each criterion i: u = conserved variable var[i] (MAP_EST_VAR) or |B|
+ * (MAP_EST_BMAG), with its own eps[i] (the paper: 1e-12 for rho, p, T and
+ * 0.1 for v, B); filt = 0.05, bias = 0.6, ratio = 2 in the paper. */
+typedef struct {
+    int ncrit;      /* criteria used, 1..4 */
+    int mode[4];    /* MAP_EST_VAR or MAP_EST_BMAG */
+    int var[4];     /* conserved variable index for MAP_EST_VAR */
+    double eps[4];
+    double filt, bias, ratio, xi;
+} map_estimator;
+
+/* Largest estimate of every block over its interior and the first ring of
+ * ghost cells (the paper checks every cell covering the ghost region), the
+ * maximum over the criteria, computed in FP64 from U (either precision):
+ * err_dev[nblocks] (device, by slot).  Ghost cells are read where the ghost
+ * descriptors point, so U may come straight from map_advance.  Parents are
+ * evaluated on their restricted data (they are the candidates for
+ * destroying their children).  Errors: MAP_EINVAL (bad criteria). */
+map_status map_estimate(map_ctx *ctx, const void *U, const map_estimator *est, double *err_dev,
+                        void *stream);
+
+typedef struct {
+    double tau_refine;   /* a leaf with a larger estimate is refined */
+    double tau_coarsen;  /* a block whose children are all leaves, none refined,
+                            loses them when its own estimate is smaller */
+    int max_level;       /* finest level allowed (base = 1) */
+} map_regrid_params;
+
+/* The block tree after one regrid (Sec. 4.5), host only: flagged leaves
+ * below max_level are refined, blocks whose estimate is below tau_coarsen
+ * lose their children, and the result is closed under 2:1 balance across
+ * faces, edges and corners (a leaf that would touch a leaf two levels finer
+ * is refined instead, or its coarsening is cancelled).  err_host[nblocks]
+ * by slot (as map_estimate writes it).  Writes the new keys, sorted by
+ * (sim, level, ix, iy, iz), to keys_out[capacity] and their count to *nout;
+ * MAP_ENOMEM (with *nout set) if capacity is too small. */
+map_status map_regrid(const map_ctx *ctx, const double *err_host, const map_regrid_params *rp,
+                      map_block_key *keys_out, int capacity, int *nout);
+
+/* Moves a state onto a new tree of the same simulations and parameters
+ * (Sec. 4.5 with the boundary procedure of Sec. 4.3): blocks present in
+ * both trees are copied; blocks new in dst (children of src leaves) are
+ * filled by the conservative prolongation of Sec. 4.3 step 6 from their
+ * parent's padded tile; then every parent is restricted from its children
+ * and all ghost frames are filled.  Blocks that lose their children keep
+ * their restricted data as leaf data.  Both contexts must be bound; a dst
+ * block absent from src must have its parent in src (one level of
+ * refinement per regrid).  Synchronises `stream`.  Errors: MAP_EINVAL,
+ * MAP_ETREE, MAP_ESTATE, MAP_EHIP. */
+map_status map_remap(map_ctx *dst, void *U_dst, const map_ctx *src, const void *U_src,
+                     void *stream);
 
 const char *map_last_error(void);
 void map_destroy(map_ctx *ctx);

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "kernels.hpp"
@@ -246,6 +247,9 @@ void drop_graph(map_ctx *c)
 }
 
 }  // namespace
+
+// error reporting for the host tree edit (regrid.cpp)
+map_status regrid_fail(map_status st, const std::string &msg) { return fail(st, msg); }
 
 extern "C" {
 
@@ -636,6 +640,102 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
         chosen[0] = best_step;
         chosen[1] = best_fill;
     }
+    return MAP_OK;
+}
+
+map_status map_estimate(map_ctx *c, const void *U, const map_estimator *est, double *err_dev,
+                        void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U || !est || !err_dev)
+        return fail(MAP_EINVAL, "null U, estimator or output");
+    if (est->ncrit < 1 || est->ncrit > 4)
+        return fail(MAP_EINVAL, "ncrit must be 1..4");
+    for (int i = 0; i < est->ncrit; i++) {
+        if (est->mode[i] != MAP_EST_VAR && est->mode[i] != MAP_EST_BMAG)
+            return fail(MAP_EINVAL, "unknown estimator mode");
+        if (est->mode[i] == MAP_EST_VAR && (est->var[i] < 0 || est->var[i] >= NV))
+            return fail(MAP_EINVAL, "estimator variable out of range");
+    }
+    EstArgs a{};
+    a.U = U;
+    a.desc = dptr<Desc>(c, c->ws.desc);
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.err = err_dev;
+    a.nslots = c->nslots;
+    a.est = *est;
+    HIPCHK(launch_estimate(c->nd, fp64(c), a, S(stream)));
+    return MAP_OK;
+}
+
+map_status map_remap(map_ctx *dst, void *Ud, const map_ctx *src, const void *Us, void *stream)
+{
+    map_status st = need_bound(dst);
+    if (st)
+        return st;
+    if (!src || !src->bound)
+        return fail(MAP_ESTATE, "source context not bound");
+    if (!Ud || !Us)
+        return fail(MAP_EINVAL, "null state");
+    if (src->nd != dst->nd || src->p.precision != dst->p.precision ||
+        src->sims.size() != dst->sims.size() ||
+        std::memcmp(src->sims.data(), dst->sims.data(), sizeof(map_sim_desc) * src->sims.size()))
+        return fail(MAP_EINVAL, "contexts differ in dimension, precision or simulations");
+    std::unordered_map<uint64_t, int> src_slot;
+    src_slot.reserve((size_t)src->nslots * 2);
+    auto pack = [](const map_block_key &k) {
+        return ((uint64_t)k.sim << 47) | ((uint64_t)k.level << 42) | ((uint64_t)k.ix << 28) |
+               ((uint64_t)k.iy << 14) | (uint64_t)k.iz;
+    };
+    for (int s = 0; s < src->nslots; s++)
+        src_slot[pack(src->key[s])] = s;
+    dst->remap_src.assign(dst->nslots, -1);
+    dst->remap_new.clear();
+    for (int s = 0; s < dst->nslots; s++) {
+        auto it = src_slot.find(pack(dst->key[s]));
+        if (it != src_slot.end()) {
+            dst->remap_src[s] = it->second;
+            continue;
+        }
+        const int p = dst->parent[s];
+        if (p < 0 || !src_slot.count(pack(dst->key[p])))
+            return fail(MAP_ETREE, "a new block's parent is not in the source tree");
+        dst->remap_new.push_back(s);
+    }
+    hipStream_t s = S(stream);
+    HIPCHK(hipMemcpyAsync(dst->wsp + dst->ws.remap, dst->remap_src.data(),
+                          sizeof(int32_t) * dst->nslots, hipMemcpyHostToDevice, s));
+    if (!dst->remap_new.empty())
+        HIPCHK(hipMemcpyAsync(dst->wsp + dst->ws.newlist, dst->remap_new.data(),
+                              sizeof(int32_t) * dst->remap_new.size(), hipMemcpyHostToDevice, s));
+    RemapArgs r{};
+    r.Udst = Ud;
+    r.Usrc = Us;
+    r.map = dptr<int32_t>(dst, dst->ws.remap);
+    r.tile_bytes = (size_t)NV * dst->tile * dst->word;
+    r.nslots = dst->nslots;
+    HIPCHK(launch_remap_copy(r, s));
+    // ghosts of the surviving blocks (the parents of new blocks are among
+    // them), then the new blocks from their parents, then restriction and
+    // a complete fill
+    if ((st = run_fill(dst, Ud, s, true)) != MAP_OK)
+        return st;
+    if (!dst->remap_new.empty()) {
+        FillArgs a{};
+        a.U = Ud;
+        a.blk = dptr<BlockRec>(dst, dst->ws.blocks);
+        a.parent = dptr<int32_t>(dst, dst->ws.parent);
+        a.list = dptr<int32_t>(dst, dst->ws.newlist);
+        a.nitems = (int)dst->remap_new.size();
+        HIPCHK(launch_prolong_blocks(dst->nd, fp64(dst), a, s));
+    }
+    if ((st = run_restrict(dst, Ud, s)) != MAP_OK)
+        return st;
+    if ((st = run_fill(dst, Ud, s, true)) != MAP_OK)
+        return st;
+    HIPCHK(hipStreamSynchronize(s));
     return MAP_OK;
 }
 

@@ -83,6 +83,23 @@ struct TotalsArgs {
     int nsims, ndim;
 };
 
+struct EstArgs {
+    const void *U;
+    const Desc *desc;
+    const BlockRec *blk;
+    double *err;
+    int nslots;
+    map_estimator est;
+};
+
+struct RemapArgs {
+    void *Udst;
+    const void *Usrc;
+    const int32_t *map;   // by destination slot: source slot or -1
+    size_t tile_bytes;    // NV x padded cells x word
+    int nslots;
+};
+
 // launchers (defined in the .hip files); return hipError_t of the launch
 hipError_t launch_step_lf(int ndim, bool fp64, bool resist, const StepArgs &a, int grid,
                           hipStream_t s);
@@ -102,5 +119,7 @@ hipError_t launch_totals(int ndim, bool fp64, const TotalsArgs &a, hipStream_t s
 hipError_t launch_prim_to_cons(bool fp64, void *U, size_t ncell_per_var_total, int tile,
                                double gamma, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_estimate(int ndim, bool fp64, const EstArgs &a, hipStream_t s);
+hipError_t launch_remap_copy(const RemapArgs &a, hipStream_t s);
 
 }  // namespace mapk

@@ -459,6 +459,8 @@ void map_plan_layout(map_ctx *c)
     L.tot_part = take((size_t)c->nleaves * NV * sizeof(double));
     L.counters = take(4 * sizeof(unsigned long long));
     L.fbuf = take((size_t)c->nfb * NV * c->face_cells() * c->word);
+    L.remap = take(n * sizeof(int32_t));
+    L.newlist = take(n * sizeof(int32_t));
     L.shadow = take(n * NV * (size_t)c->tile * c->word);
     L.total = o;
 }

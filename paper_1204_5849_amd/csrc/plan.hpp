@@ -44,6 +44,10 @@ struct map_ctx {
     int launch_mode = MAP_LAUNCH_BATCHED;
     int grid_step = 0, grid_fill = 0;
 
+    // map_remap: by slot, the source slot in the previous tree (-1: new
+    // block), and the new blocks (host copies kept for the async upload)
+    std::vector<int32_t> remap_src, remap_new;
+
     // captured cycle
     void *graph_exec = nullptr;  // hipGraphExec_t
     void *graph_U = nullptr;

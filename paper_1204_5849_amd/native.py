@@ -19,6 +19,7 @@ MAP_MINMOD, MAP_VANLEER, MAP_PAPER_PHI = 0, 1, 2
 MAP_GLM_PAPER, MAP_GLM_FASTSPEED = 0, 1
 MAP_BC_PERIODIC, MAP_BC_OUTFLOW = 0, 1
 MAP_LAUNCH_BATCHED, MAP_LAUNCH_PER_BLOCK = 0, 1
+MAP_EST_VAR, MAP_EST_BMAG = 0, 1
 
 SCHEMES = {"lf": MAP_LF, "mmc": MAP_MMC}
 LIMITERS = {"minmod": MAP_MINMOD, "vanleer": MAP_VANLEER, "paper": MAP_PAPER_PHI}
@@ -29,7 +30,8 @@ PRECISION = {"fp64": MAP_FP64, "fp32": MAP_FP32_MIXED}
 EXPORTS = ["map_init_blocks", "map_query", "map_neighbors", "map_bind_workspace",
            "map_prim_to_cons", "map_fill_ghosts", "map_restrict", "map_prolong", "map_cfl_dt",
            "map_step", "map_reflux", "map_totals", "map_status_flags", "map_advance",
-           "map_graph_run", "map_set_launch", "map_autotune", "map_last_error", "map_destroy"]
+           "map_graph_run", "map_set_launch", "map_autotune", "map_estimate", "map_regrid",
+           "map_remap", "map_last_error", "map_destroy"]
 
 
 class MapError(RuntimeError):
@@ -68,6 +70,16 @@ class map_sizes(C.Structure):
                 ("n_face_buffers", C.c_int)]
 
 
+class map_estimator(C.Structure):
+    _fields_ = [("ncrit", C.c_int), ("mode", C.c_int * 4), ("var", C.c_int * 4),
+                ("eps", C.c_double * 4), ("filt", C.c_double), ("bias", C.c_double),
+                ("ratio", C.c_double), ("xi", C.c_double)]
+
+
+class map_regrid_params(C.Structure):
+    _fields_ = [("tau_refine", C.c_double), ("tau_coarsen", C.c_double), ("max_level", C.c_int)]
+
+
 _lib = None
 
 
@@ -98,6 +110,10 @@ def lib():
         L.map_graph_run.argtypes = [vp, vp, vp, C.c_int, vp]
         L.map_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.map_autotune.argtypes = [vp, vp, C.POINTER(C.c_int), vp]
+        L.map_estimate.argtypes = [vp, vp, C.POINTER(map_estimator), vp, vp]
+        L.map_regrid.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(map_regrid_params),
+                                 C.POINTER(map_block_key), C.c_int, C.POINTER(C.c_int)]
+        L.map_remap.argtypes = [vp, vp, vp, vp, vp]
         L.map_last_error.restype = C.c_char_p
         L.map_last_error.argtypes = []
         L.map_destroy.argtypes = [vp]
@@ -243,6 +259,44 @@ def map_autotune(ctx, U, stream):
     arr = (C.c_int * 2)()
     check(lib().map_autotune(ctx, _p(U), arr, _p(stream)))
     return int(arr[0]), int(arr[1])
+
+
+def make_estimator(criteria, filt=0.05, bias=0.6, ratio=2.0, xi=0.0):
+    """criteria: up to 4 tuples (mode, var, eps) with mode "var" (conserved
+    variable index var) or "bmag" (|B|)."""
+    e = map_estimator()
+    e.ncrit = len(criteria)
+    for i, (mode, var, eps) in enumerate(criteria):
+        e.mode[i] = {"var": MAP_EST_VAR, "bmag": MAP_EST_BMAG}.get(mode, mode)
+        e.var[i] = var
+        e.eps[i] = eps
+    e.filt, e.bias, e.ratio, e.xi = filt, bias, ratio, xi
+    return e
+
+
+def map_estimate(ctx, U, est, err_dev, stream):
+    check(lib().map_estimate(ctx, _p(U), C.byref(est), _p(err_dev), _p(stream)))
+
+
+def map_regrid(ctx, err_host, tau_refine, tau_coarsen, max_level):
+    """New keys (int32 [n, 5], sorted) from per-slot estimates (float64)."""
+    import numpy as np
+    err = np.ascontiguousarray(np.asarray(err_host, dtype=np.float64))
+    rp = map_regrid_params(tau_refine, tau_coarsen, max_level)
+    n = C.c_int(0)
+    st = lib().map_regrid(ctx, err.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rp), None, 0,
+                          C.byref(n))
+    if st not in (MAP_OK, MAP_ENOMEM):
+        check(st)
+    out = (map_block_key * max(n.value, 1))()
+    check(lib().map_regrid(ctx, err.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rp), out,
+                           n.value, C.byref(n)))
+    keys = np.frombuffer(out, dtype=np.int32, count=5 * n.value).reshape(n.value, 5).copy()
+    return keys
+
+
+def map_remap(dst_ctx, U_dst, src_ctx, U_src, stream):
+    check(lib().map_remap(dst_ctx, _p(U_dst), src_ctx, _p(U_src), _p(stream)))
 
 
 def map_destroy(ctx):

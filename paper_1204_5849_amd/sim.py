@@ -137,5 +137,32 @@ class Simulation:
     def autotune(self):
         return N.map_autotune(self.ctx, self.U, self.sp)
 
+    # ---------------------------------------------------------------- regrid
+    def estimate(self, criteria, filt=0.05, bias=0.6, ratio=2.0, xi=0.0):
+        """Per-block regrid estimate (Sec. 4.5) in the caller's key order
+        (float64 numpy); criteria as in native.make_estimator."""
+        est = N.make_estimator(criteria, filt=filt, bias=bias, ratio=ratio, xi=xi)
+        err = torch.zeros(self.nslots, dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize(self.device)
+        N.map_estimate(self.ctx, self.U, est, err, self.sp)
+        self.stream.synchronize()
+        return err.cpu().numpy()[self.slot_of_key]
+
+    def regrid(self, criteria, tau_refine, tau_coarsen, max_level, **est_kw):
+        """One regrid: estimate on device, the tree edit on the host, and the
+        state moved onto the new tree on device.  Returns a new Simulation
+        (this one is left unchanged)."""
+        import dataclasses
+        est = N.make_estimator(criteria, **est_kw)
+        err = torch.zeros(self.nslots, dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize(self.device)
+        N.map_estimate(self.ctx, self.U, est, err, self.sp)
+        self.stream.synchronize()
+        keys = N.map_regrid(self.ctx, err.cpu().numpy(), tau_refine, tau_coarsen, max_level)
+        wl = dataclasses.replace(self.wl, keys=keys)
+        new = Simulation(wl, device=self.device, stream=self.stream, precision=self.precision)
+        N.map_remap(new.ctx, new.U, self.ctx, self.U, self.sp)
+        return new
+
     def sync(self):
         self.stream.synchronize()

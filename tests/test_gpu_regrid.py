@@ -1,0 +1,183 @@
+"""GPU parity of the regrid path (paper Sec. 4.5) against the oracle: the
+error estimator per block, the state moved onto a new tree (copies,
+prolongation of new blocks, restriction, fill), and cycles after a regrid."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle.regrid import regrid as oracle_regrid  # noqa: E402
+from paper_1204_5849_amd import native as N  # noqa: E402
+from paper_1204_5849_amd import workloads as W  # noqa: E402
+from tests.helpers import rel_linf  # noqa: E402
+
+CRIT = [("var", 0, 1e-12), ("bmag", 0, 0.1)]
+
+
+def _say(msg):
+    print(f"[gpu-regrid] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    N.lib()
+    return "cuda:0"
+
+
+def _sim(w, **kw):
+    from paper_1204_5849_amd.sim import Simulation
+    s = Simulation(w, **kw)
+    s.load_initial()
+    return s
+
+
+def _oracle_err(orc, w, U):
+    p = orc.params_from_workload(w)
+    n3 = (16, 16, 16) if w.ndim == 3 else (16, 16, 1)
+    out = np.zeros(len(w.keys))
+    for b in range(len(w.keys)):
+        lv = int(w.keys[b, 1])
+        t = np.ascontiguousarray(U[b])
+        out[b] = max(orc.estimate(p, t, n3, 0, 0, eps=1e-12, level=lv),
+                     orc.estimate(p, t, n3, 1, 0, eps=0.1, level=lv))
+    return out
+
+
+def _workload(name, precision):
+    if name == "blast":
+        return W.blast3d(nbase=2, levels=2, precision=precision)
+    return W.harris3d(nbase=2, levels=3, precision=precision)
+
+
+def _tree2d(precision):
+    """Orszag-Tang on an 8 x 8 base with the left half refined once."""
+    base = W.orszag_tang(8)
+    keys = base.keys
+    kids = W.children_of(keys[(keys[:, 2] < 4)], 2)
+    return W.ot_amr(np.concatenate([keys, kids]), nbase=8, precision=precision)
+
+
+@pytest.mark.parametrize("name,precision", [("ot", "fp64"), ("ot", "fp32"), ("blast", "fp64"),
+                                            ("harris", "fp32")])
+def test_estimate_matches_oracle(dev, orc, name, precision):
+    w = _tree2d(precision) if name == "ot" else _workload(name, precision)
+    _say(f"estimate {name} {precision}: {len(w.keys)} blocks")
+    s = _sim(w)
+    s.advance(2)  # ghost frames are left unspecified by the cycle: the estimate reads in place
+    got = s.estimate(CRIT)
+    s.fill()
+    want = _oracle_err(orc, w, s.state_by_key())
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-300)
+    _say(f"  max rel diff {rel.max():.2e}, estimates in [{want.min():.3g}, {want.max():.3g}]")
+    assert rel.max() <= 1e-12
+
+
+def _interior(w, U):
+    if w.ndim == 3:
+        return U[:, :, 2:-2, 2:-2, 2:-2]
+    return U[:, :, :, 2:-2, 2:-2]
+
+
+def _thresholds(w, err):
+    """Refine the top fifth of the leaves; destroy the children of the
+    smoother half of the blocks whose children are all leaves.  Thresholds
+    sit at midpoints between sorted estimates, so none is on a threshold."""
+    leaves = w.leaf_mask()
+    le = np.sort(np.unique(err[leaves]))
+    tr = 0.5 * (le[int(0.8 * len(le))] + le[int(0.8 * len(le)) - 1])
+    keyset = {tuple(int(v) for v in k) for k in w.keys}
+    cand = []
+    for i, k in enumerate(w.keys):
+        if leaves[i]:
+            continue
+        s, lv, x, y, z = (int(v) for v in k)
+        kids = [(s, lv + 1, 2 * x + (c & 1), 2 * y + ((c >> 1) & 1),
+                 2 * z + ((c >> 2) & 1) if w.ndim == 3 else 0) for c in range(1 << w.ndim)]
+        kid_parents = {(s2, l2 - 1, x2 >> 1, y2 >> 1, z2 >> 1) for (s2, l2, x2, y2, z2) in keyset}
+        if all(c in keyset and c not in kid_parents for c in kids):
+            cand.append(err[i])
+    pe = np.sort(np.unique(cand))
+    if len(pe) > 1:
+        tc = 0.5 * (pe[len(pe) // 2] + pe[len(pe) // 2 - 1])
+    else:  # all candidates alike (a symmetric problem): all of them qualify
+        tc = pe[0] * (1.0 + 1e-6) + 1e-300
+    return tr, tc
+
+
+def _changes(w_old, w_new):
+    old = {tuple(int(v) for v in k) for k in w_old.keys}
+    new = {tuple(int(v) for v in k) for k in w_new.keys}
+    return len(new - old), len(old - new)
+
+
+def _oracle_remap(orc, w_new, w_old, old_full):
+    p = orc.params_from_workload(w_new)
+    B = orc.Amr(p, 16, w_new.sims, w_new.keys)
+    old_index = {tuple(int(v) for v in k): i for i, k in enumerate(w_old.keys)}
+    new_blocks = []
+    for i, k in enumerate(w_new.keys):
+        j = old_index.get(tuple(int(v) for v in k))
+        if j is None:
+            new_blocks.append(i)
+        else:
+            B.state[i] = old_full[j]
+    B.fill()
+    for i in new_blocks:
+        B.prolong_block(i)
+    B.restrict()
+    B.fill()
+    return B, new_blocks
+
+
+@pytest.mark.parametrize("name", ["ot", "blast"])
+def test_remap_matches_oracle(dev, orc, name):
+    # 3-D: a 4^3 base, so that smooth blocks can lose their children without
+    # touching the new finest blocks (on a 2^3 periodic base every block
+    # touches every other)
+    w = _tree2d("fp64") if name == "ot" else W.blast3d(nbase=4, levels=2, precision="fp64")
+    s = _sim(w)
+    s.advance(2)
+    err = s.estimate(CRIT)
+    tr, tc = _thresholds(w, err)
+    new = s.regrid(CRIT, tr, tc, 3)
+    want_keys = oracle_regrid([tuple(k) for k in w.keys], w.sims, w.ndim,
+                              {tuple(int(v) for v in k): e for k, e in zip(w.keys, err)}, tr, tc, 3)
+    assert [tuple(int(v) for v in k) for k in new.wl.keys] == want_keys
+    s.fill()
+    B, new_blocks = _oracle_remap(orc, new.wl, w, s.state_by_key())
+    created, destroyed = _changes(w, new.wl)
+    _say(f"remap {name}: {len(w.keys)} -> {len(new.wl.keys)} blocks, {created} created, "
+         f"{destroyed} destroyed (tau_refine {tr:.3g}, tau_coarsen {tc:.3g})")
+    assert created == len(new_blocks) and created > 0 and destroyed > 0
+    assert np.array_equal(new.state_by_key(), B.state)
+
+
+@pytest.mark.parametrize("name", ["ot", "blast"])
+def test_regrid_then_cycles_match_oracle(dev, orc, name):
+    """Cycles, a regrid that refines and coarsens, more cycles: the leaves
+    agree with the oracle doing the same (FP64)."""
+    w = _tree2d("fp64") if name == "ot" else _workload(name, "fp64")
+    s = _sim(w)
+    A = orc.load_workload(w)
+    s.advance(3)
+    A.run(3)
+    err = s.estimate(CRIT)
+    tr, tc = _thresholds(w, err)
+    new = s.regrid(CRIT, tr, tc, 3)
+    s.fill()
+    # the oracle starts from its own state
+    B, _ = _oracle_remap(orc, new.wl, w, A.state)
+    new.advance(4)
+    B.run(4)
+    leaves = new.wl.leaf_mask()
+    g = _interior(new.wl, new.state_by_key()[leaves])
+    o = _interior(new.wl, B.state[leaves])
+    err8 = rel_linf(g, o)
+    created, destroyed = _changes(w, new.wl)
+    _say(f"{name} regrid ({created} created, {destroyed} destroyed) + 4 cycles: "
+         f"rel Linf per var {np.array2string(err8, precision=2)}")
+    assert np.all(err8[:8] <= 1e-11)
