@@ -26,37 +26,48 @@ __device__ __forceinline__ double est_value(const EstArgs &a, int i, int slot, i
 }
 
 // largest estimate over the interior and the first ghost ring of each block,
-// maximum over the criteria; one workgroup per block
+// maximum over the criteria; one workgroup per block.  Each criterion's value
+// is formed once per padded cell (ghosts read where the descriptors point)
+// and staged in LDS; the stencil then runs on LDS.
 template <int NDIM, typename T>
 __global__ void __launch_bounds__(NTE) k_estimate(EstArgs a)
 {
+    constexpr int PT = tile_cells<NDIM>();
+    __shared__ double sv[PT];
     __shared__ double red[NTE / 64];
     constexpr int E = NB + 2;
     constexpr int NE = NDIM == 3 ? E * E * E : E * E;
+    const int st[3] = {1, PD, PD * PD};
     for (int slot = blockIdx.x; slot < a.nslots; slot += gridDim.x) {
         const int level = a.blk[slot].level;
         const double scale = pow(a.est.ratio, a.est.xi * (level - 1));
         double best = 0.0;
-        for (int c = threadIdx.x; c < NE; c += NTE) {
-            const int x = c % E - 1, y = (c / E) % E - 1, z = NDIM == 3 ? c / (E * E) - 1 : 0;
-            for (int i = 0; i < a.est.ncrit; i++) {
-                const double v = est_value<NDIM, T>(a, i, slot, x, y, z);
+        for (int i = 0; i < a.est.ncrit; i++) {
+            for (int c = threadIdx.x; c < PT; c += NTE) {
+                const int x = c % PD - NG, y = (c / PD) % PD - NG;
+                const int z = NDIM == 3 ? c / (PD * PD) - NG : 0;
+                sv[c] = est_value<NDIM, T>(a, i, slot, x, y, z);
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < NE; e += NTE) {
+                const int x = e % E - 1, y = (e / E) % E - 1, z = NDIM == 3 ? e / (E * E) - 1 : 0;
+                const int c = lin<NDIM>(x, y, z);
+                const double v = sv[c];
                 double s1 = 0.0, s2 = 0.0;
 #pragma unroll
                 for (int d = 0; d < NDIM; d++) {
-                    const int ox = d == 0, oy = d == 1, oz = d == 2;
-                    const double vp = est_value<NDIM, T>(a, i, slot, x + ox, y + oy, z + oz);
-                    const double vm = est_value<NDIM, T>(a, i, slot, x - ox, y - oy, z - oz);
+                    const double vp = sv[c + st[d]], vm = sv[c - st[d]];
                     s1 += (vp - vm) * (vp - vm);
                     s2 += (vp - 2.0 * v + vm) * (vp - 2.0 * v + vm);
                 }
                 const double d1 = 0.5 * sqrt(3.0) * sqrt(s1);
                 const double d2 = sqrt(s2);
                 const double av = fabs(v) + a.est.eps[i];
-                const double e =
+                const double est =
                     (a.est.bias * d1 / av + (1.0 - a.est.bias) * d2 / (d1 + a.est.filt * av)) * scale;
-                best = e > best ? e : best;
+                best = est > best ? est : best;
             }
+            __syncthreads();  // sv is restaged for the next criterion / block
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {

@@ -148,6 +148,12 @@ class Simulation:
         self.stream.synchronize()
         return err.cpu().numpy()[self.slot_of_key]
 
+    def regrid_interval(self, c_r=1.0):
+        """Steps between regrids, Sec. 4.5: dt_r = c_r 2 n_g n_dim dt / c_cfl
+        (a wave cannot cross the 2 n_g buffer cells of a refined region in
+        that time)."""
+        return max(1, int(c_r * 2 * NG * self.wl.ndim / self.wl.cfl))
+
     def regrid(self, criteria, tau_refine, tau_coarsen, max_level, **est_kw):
         """One regrid: estimate on device, the tree edit on the host, and the
         state moved onto the new tree on device.  Returns a new Simulation
