@@ -24,12 +24,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 MHD, SCALAR = 0, 1
-LF, MMC = 0, 1
+LF, MMC, WENO = 0, 1, 2
 MINMOD, VANLEER, PAPER_PHI = 0, 1, 2
 GLM_PAPER, GLM_FASTSPEED = 0, 1
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 
-_SCHEMES = {"lf": LF, "mmc": MMC}
+_SCHEMES = {"lf": LF, "mmc": MMC, "weno": WENO}
 _LIMITERS = {"minmod": MINMOD, "vanleer": VANLEER, "paper": PAPER_PHI}
 _GLM = {"paper": GLM_PAPER, "fastspeed": GLM_FASTSPEED}
 _BC = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW}
@@ -93,6 +93,8 @@ def lib():
         L.orc_speed.restype = C.c_double
         L.orc_limiter.argtypes = [C.c_int, C.c_double, C.c_double]
         L.orc_limiter.restype = C.c_double
+        L.orc_weno_face.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
+        L.orc_weno_face.restype = C.c_double
         L.orc_prim_to_cons.argtypes = [pp, dp, C.c_long]
         L.orc_step_tile.argtypes = [pp, dp, dp, ip, C.POINTER(DtRec), dp, dp, lp]
         L.orc_eglm_source.argtypes = [pp, dp, dp, ip, dp]
@@ -182,6 +184,11 @@ def speed(p, u, dim):
 def limiter(kind, a, b):
     kind = _LIMITERS.get(kind, kind)
     return lib().orc_limiter(kind, float(a), float(b))
+
+
+def weno_face(um, u0, up, side):
+    """WENO face state from three cells: side 0 = u^-_{i+1/2}, 1 = u^+_{i-1/2}."""
+    return lib().orc_weno_face(float(um), float(u0), float(up), int(side))
 
 
 def prim_to_cons(p, w):

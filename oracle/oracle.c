@@ -303,6 +303,79 @@ static void lf_faces(const orc_params *p, const geo *G, const double *ut,
             }
 }
 
+/* WENO (Sec. 3.3, component-wise, third order): the states either side of
+ * a face from the three cells around each of them, with the smoothness
+ * weights a = 1 / (eps + (difference)^2)^2, eps = 1e-12.  The printed
+ * denominator of u+ repeats a_{i-1/2}; the weights 1 and 2 of its numerator
+ * are read as the denominator a_{i+1/2} + 2 a_{i-1/2}. */
+#define WENO_EPS 1e-12
+static double sq(double a) { return a * a; }
+
+/* u^-_{i+1/2} from u_{i-1}, u_i, u_{i+1} */
+static double weno_minus(double um, double u0, double up)
+{
+    double ap = 1.0 / sq(WENO_EPS + sq(up - u0));
+    double am = 1.0 / sq(WENO_EPS + sq(u0 - um));
+    double w = 0.5 * (u0 + up);
+    double v = 0.5 * (3.0 * u0 - um);
+    return (2.0 * ap * w + am * v) / (2.0 * ap + am);
+}
+
+/* u^+_{i-1/2} from u_{i-1}, u_i, u_{i+1} */
+static double weno_plus(double um, double u0, double up)
+{
+    double ap = 1.0 / sq(WENO_EPS + sq(up - u0));
+    double am = 1.0 / sq(WENO_EPS + sq(u0 - um));
+    double w = 0.5 * (3.0 * u0 - up);
+    double v = 0.5 * (u0 + um);
+    return (ap * w + 2.0 * am * v) / (ap + 2.0 * am);
+}
+
+double orc_weno_face(double um, double u0, double up, int side)
+{
+    return side ? weno_plus(um, u0, up) : weno_minus(um, u0, up);
+}
+
+/* Rusanov flux (Equ:LFFlux) at every face i+1/2 along d from the WENO
+ * states; a face state with rho <= 0 or p <= 0 falls back to its cell's
+ * value (the same fall-back as the LF scheme). */
+static void weno_faces(const orc_params *p, const geo *G, const double *u, int d, double ch,
+                       double *fh, long *cnt)
+{
+    int nv = orc_nvar(p);
+    long P = G->P, s = G->s[d];
+    int lo[3] = {0, 0, 0}, hi[3] = {G->n[0], G->n[1], G->n[2]};
+    lo[d] = -1;
+    hi[d] = G->n[d];
+    for (int z = lo[2]; z < hi[2]; z++)
+        for (int y = lo[1]; y < hi[1]; y++)
+            for (int x = lo[0]; x < hi[0]; x++) {
+                long c = at(G, x, y, z), cn = c + s;
+                double L[NVMAX], R[NVMAX], FL[NVMAX], FR[NVMAX];
+                for (int k = 0; k < nv; k++) {
+                    const double *q = u + k * P;
+                    L[k] = weno_minus(q[c - s], q[c], q[cn]);
+                    R[k] = weno_plus(q[c], q[cn], q[cn + s]);
+                }
+                if (!admissible(p, L)) {
+                    load(u, P, nv, c, L);
+                    cnt[1]++;
+                }
+                if (!admissible(p, R)) {
+                    load(u, P, nv, cn, R);
+                    cnt[1]++;
+                }
+                orc_flux(p, L, d, ch, FL);
+                orc_flux(p, R, d, ch, FR);
+                double aL = orc_speed(p, L, d), aR = orc_speed(p, R, d);
+                double a = aL > aR ? aL : aR;
+                for (int k = 0; k < nv; k++) {
+                    double al = glm_component(p, k, d) ? ch : a;
+                    fh[k * P + c] = 0.5 * (FL[k] + FR[k]) - 0.5 * al * (R[k] - L[k]);
+                }
+            }
+}
+
 /* MMC (Sec. 3.1): Lax-Friedrichs splitting f+- = (f +- alpha u)/2 with the
  * global alpha (c_h on the GLM pair), predictor with h = f+_i + f-_{i+1},
  * and the flux-limited correction with g+ and g- built from u~. */
@@ -519,6 +592,10 @@ void orc_step_tile(const orc_params *p, const double dx[3], const double *u,
             lf_faces(p, &G, ut, sl, d, dt->ch, fh[d], cnt);
         free(ut);
         free(sl);
+    } else if (p->scheme == ORC_WENO) {
+        /* one Euler stage: the fluxes of every direction from the same u */
+        for (int d = 0; d < nd; d++)
+            weno_faces(p, &G, u, d, dt->ch, fh[d], cnt);
     } else {
         mmc_fluxes(p, &G, u, dtdx, dt, fh);
     }
@@ -556,8 +633,10 @@ void orc_step_tile(const orc_params *p, const double dx[3], const double *u,
                             v[BX + j] = v[BX + j] + dt->dt * res[(BX + j) * G.I + ic];
                         v[EN] = v[EN] + dt->dt * res[EN * G.I + ic];
                     }
-                    /* MHD-5 damping term integrated exactly over dt */
-                    v[PSI] = v[PSI] * dt->damp;
+                    /* MHD-5 damping term integrated exactly over dt (for WENO
+                     * once per step, after the second Runge-Kutta stage) */
+                    if (p->scheme != ORC_WENO)
+                        v[PSI] = v[PSI] * dt->damp;
                 }
                 for (int k = 0; k < nv; k++)
                     unew[k * G.I + ic] = v[k];
@@ -689,6 +768,30 @@ void orc_grid_run(const orc_params *p, const double dx[3], double *u, const int 
         if (dt_trace)
             dt_trace[it] = r.dt;
         orc_step_tile(p, dx, u, n_in, &r, unew, NULL, cnt);
+        if (p->scheme == ORC_WENO) {
+            /* TVD Runge-Kutta 2: u1 = u + dt L(u); u = (u + u1 + dt L(u1)) / 2 */
+            double *u1 = malloc(sizeof(double) * nv * G.P);
+            memcpy(u1, u, sizeof(double) * nv * G.P);
+            for (int z = 0; z < G.n[2]; z++)
+                for (int y = 0; y < G.n[1]; y++)
+                    for (int x = 0; x < G.n[0]; x++)
+                        for (int k = 0; k < nv; k++)
+                            u1[k * G.P + at(&G, x, y, z)] =
+                                unew[k * G.I + interior_index(&G, x, y, z)];
+            orc_grid_fill(p, u1, n_in, bc);
+            orc_step_tile(p, dx, u1, n_in, &r, unew, NULL, cnt);
+            free(u1);
+            for (int z = 0; z < G.n[2]; z++)
+                for (int y = 0; y < G.n[1]; y++)
+                    for (int x = 0; x < G.n[0]; x++) {
+                        long c = at(&G, x, y, z), ic = interior_index(&G, x, y, z);
+                        for (int k = 0; k < nv; k++)
+                            u[k * G.P + c] = 0.5 * (u[k * G.P + c] + unew[k * G.I + ic]);
+                        if (p->physics == ORC_MHD)
+                            u[PSI * G.P + c] = u[PSI * G.P + c] * r.damp;
+                    }
+            continue;
+        }
         for (int z = 0; z < G.n[2]; z++)
             for (int y = 0; y < G.n[1]; y++)
                 for (int x = 0; x < G.n[0]; x++)
@@ -1043,8 +1146,14 @@ void orc_amr_cfl(orc_amr *A, orc_dtrec *out)
     }
 }
 
+static void amr_weno_rk2(orc_amr *A, const orc_dtrec *dt);
+
 void orc_amr_step(orc_amr *A, const orc_dtrec *dt)
 {
+    if (A->p.scheme == ORC_WENO) {
+        amr_weno_rk2(A, dt);
+        return;
+    }
     geo *G = &A->G;
     int nn[3] = {A->n, A->n, A->n};
     double *unew = malloc(sizeof(double) * A->nv * G->I);
@@ -1062,6 +1171,69 @@ void orc_amr_step(orc_amr *A, const orc_dtrec *dt)
                     for (int k = 0; k < A->nv; k++)
                         u[k * G->P + at(G, x, y, z)] = unew[k * G->I + interior_index(G, x, y, z)];
     }
+    free(unew);
+}
+
+/* WENO with TVD Runge-Kutta 2 on the tree: stage 1 on every leaf into a
+ * second state, the boundary procedure (restriction, ghost exchange,
+ * prolongation) on that state, stage 2 from it; psi damping once; the face
+ * fluxes for reflux are the stage average (F + F1) / 2, which is the flux
+ * the two stages apply in total. */
+static void amr_weno_rk2(orc_amr *A, const orc_dtrec *dt)
+{
+    geo *G = &A->G;
+    int nn[3] = {A->n, A->n, A->n};
+    int nv = A->nv;
+    size_t ntot = (size_t)A->nb * nv * G->P;
+    size_t nff = (size_t)A->nb * 2 * A->nd * nv * A->T;
+    double *U1 = malloc(sizeof(double) * ntot);
+    double *ff1 = calloc(nff, sizeof(double));
+    double *unew = malloc(sizeof(double) * nv * G->I);
+    memcpy(U1, A->U, sizeof(double) * ntot);
+    for (int b = 0; b < A->nb; b++) {
+        if (A->haskids[b])
+            continue;
+        double dx[3];
+        block_dx(A, b, dx);
+        orc_step_tile(&A->p, dx, tile(A, b), nn, &dt[A->keys[b].sim], unew,
+                      ff1 + (size_t)b * 2 * A->nd * nv * A->T, A->cnt);
+        double *u1 = U1 + (size_t)b * nv * G->P;
+        for (int z = 0; z < G->n[2]; z++)
+            for (int y = 0; y < G->n[1]; y++)
+                for (int x = 0; x < G->n[0]; x++)
+                    for (int k = 0; k < nv; k++)
+                        u1[k * G->P + at(G, x, y, z)] = unew[k * G->I + interior_index(G, x, y, z)];
+    }
+    /* the boundary procedure on the stage state */
+    double *U0 = A->U;
+    A->U = U1;
+    orc_amr_restrict(A);
+    orc_amr_fill(A);
+    A->U = U0;
+    for (int b = 0; b < A->nb; b++) {
+        if (A->haskids[b])
+            continue;
+        double dx[3];
+        block_dx(A, b, dx);
+        const orc_dtrec *r = &dt[A->keys[b].sim];
+        double *ff = A->ff + (size_t)b * 2 * A->nd * nv * A->T;
+        orc_step_tile(&A->p, dx, U1 + (size_t)b * nv * G->P, nn, r, unew, ff, A->cnt);
+        double *u = tile(A, b);
+        for (int z = 0; z < G->n[2]; z++)
+            for (int y = 0; y < G->n[1]; y++)
+                for (int x = 0; x < G->n[0]; x++) {
+                    long c = at(G, x, y, z), ic = interior_index(G, x, y, z);
+                    for (int k = 0; k < nv; k++)
+                        u[k * G->P + c] = 0.5 * (u[k * G->P + c] + unew[k * G->I + ic]);
+                    if (A->p.physics == ORC_MHD)
+                        u[PSI * G->P + c] = u[PSI * G->P + c] * r->damp;
+                }
+        const double *f1 = ff1 + (size_t)b * 2 * A->nd * nv * A->T;
+        for (size_t i = 0; i < (size_t)2 * A->nd * nv * A->T; i++)
+            ff[i] = 0.5 * f1[i] + 0.5 * ff[i];
+    }
+    free(U1);
+    free(ff1);
     free(unew);
 }
 

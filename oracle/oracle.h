@@ -23,7 +23,7 @@ extern "C" {
 #endif
 
 enum { ORC_MHD = 0, ORC_SCALAR = 1 };
-enum { ORC_LF = 0, ORC_MMC = 1 };
+enum { ORC_LF = 0, ORC_MMC = 1, ORC_WENO = 2 };
 enum { ORC_MINMOD = 0, ORC_VANLEER = 1, ORC_PAPER_PHI = 2 };
 enum { ORC_GLM_PAPER = 0, ORC_GLM_FASTSPEED = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
@@ -31,7 +31,7 @@ enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
 typedef struct {
     int ndim;          /* 2 or 3 */
     int physics;       /* ORC_MHD or ORC_SCALAR */
-    int scheme;        /* ORC_LF or ORC_MMC */
+    int scheme;        /* ORC_LF, ORC_MMC, or ORC_WENO (with TVD Runge-Kutta 2) */
     int limiter;       /* slope limiter (LF) or flux limiter (MMC) */
     int glm_mode;      /* how c_h and the psi damping factor follow from dt */
     int eglm_sources;  /* 1: EGLM source terms on, 0: plain GLM */
@@ -60,6 +60,10 @@ void   orc_flux(const orc_params *p, const double *u, int dim, double ch,
                 double *f);
 double orc_speed(const orc_params *p, const double *u, int dim);
 double orc_limiter(int kind, double a, double b);
+/* WENO face state (Sec. 3.3) from the cells i-1, i, i+1: side 0 gives
+ * u^-_{i+1/2} (left state of the face right of cell i), side 1 gives
+ * u^+_{i-1/2} (right state of the face left of cell i). */
+double orc_weno_face(double um, double u0, double up, int side);
 void   orc_prim_to_cons(const orc_params *p, double *w, long ncell);
 
 /* ---- one padded tile (any interior size n[0] x n[1] x n[2]) ----

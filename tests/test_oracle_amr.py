@@ -21,7 +21,7 @@ def _assemble(orc, p, w, A, N):
     return big
 
 
-@pytest.mark.parametrize("scheme,limiter", [("lf", "minmod"), ("mmc", "vanleer")])
+@pytest.mark.parametrize("scheme,limiter", [("lf", "minmod"), ("mmc", "vanleer"), ("weno", "minmod")])
 def test_blocked_equals_monolithic_bitwise_2d(orc, scheme, limiter):
     w = W.orszag_tang(nbase=4, scheme=scheme, limiter=limiter)
     A = orc.load_workload(w)
@@ -81,11 +81,12 @@ def _tree_workload(ndim, scheme, limiter, seed, levels=3, eglm=True):
 
 
 @pytest.mark.parametrize("ndim", [2, 3])
-@pytest.mark.parametrize("scheme,limiter", [("lf", "minmod"), ("mmc", "vanleer")])
+@pytest.mark.parametrize("scheme,limiter", [("lf", "minmod"), ("mmc", "vanleer"), ("weno", "minmod")])
 def test_glm_conserves_on_amr_tree(orc, ndim, scheme, limiter):
     """GLM mode on a random 2:1-balanced periodic tree: with reflux, the
     volume-weighted totals of mass, momentum, energy and B are conserved."""
-    w = _tree_workload(ndim, scheme, limiter, seed=ndim * 10 + (scheme == "mmc"), eglm=False)
+    w = _tree_workload(ndim, scheme, limiter, seed=ndim * 10 + ["lf", "mmc", "weno"].index(scheme),
+                       eglm=False)
     A = orc.load_workload(w)
     assert (A.keys[:, 1] == 3).any()
     t0 = _exact_totals(A, w)
@@ -100,7 +101,7 @@ def test_glm_conserves_on_amr_tree(orc, ndim, scheme, limiter):
 def test_uniform_state_bitwise_on_amr_tree(orc, ndim):
     w = _tree_workload(ndim, "lf", "minmod", seed=7 + ndim)
     w.ic = lambda wl, sim, lv, x, y, z, g: [1.2, 0.3, -0.2, 0.1, 0.4, 0.5, -0.6, 0.9, 0.0]
-    for scheme in ("lf", "mmc"):
+    for scheme in ("lf", "mmc", "weno"):
         w.scheme = scheme
         A = orc.load_workload(w)
         s0 = A.state.copy()

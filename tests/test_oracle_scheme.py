@@ -96,7 +96,7 @@ def _uniform_tile(orc, p, n, w):
 
 @pytest.mark.parametrize("ndim", [2, 3])
 @pytest.mark.parametrize("scheme,limiter", [("lf", "minmod"), ("lf", "vanleer"), ("mmc", "vanleer"),
-                                            ("mmc", "minmod")])
+                                            ("mmc", "minmod"), ("weno", "minmod")])
 def test_uniform_state_is_preserved_bitwise(orc, ndim, scheme, limiter):
     p = orc.make_params(ndim=ndim, scheme=scheme, limiter=limiter, eta=1e-3 if ndim == 3 else 0.0)
     n = (8, 8, 8) if ndim == 3 else (12, 12, 1)
@@ -108,9 +108,11 @@ def test_uniform_state_is_preserved_bitwise(orc, ndim, scheme, limiter):
     assert np.array_equal(tile, u0)
 
 
-def test_psi_of_uniform_field_decays_by_cd_per_step(orc):
-    """Uniform state with psi0 != 0: only the damping term acts, psi_k = psi0 c_d^k."""
-    p = orc.make_params(ndim=2, cd=0.18)
+@pytest.mark.parametrize("scheme", ["lf", "mmc", "weno"])
+def test_psi_of_uniform_field_decays_by_cd_per_step(orc, scheme):
+    """Uniform state with psi0 != 0: only the damping term acts, psi_k = psi0 c_d^k
+    (once per step also with the two Runge-Kutta stages of WENO)."""
+    p = orc.make_params(ndim=2, cd=0.18, scheme=scheme)
     n = (8, 8, 1)
     tile = _uniform_tile(orc, p, n, [1.0, 0.1, 0.2, 0.0, 0.3, 0.4, 0.0, 1.0, 0.5])
     u0 = tile.copy()
@@ -131,7 +133,7 @@ def _ot_grid(orc, p, N):
     return big, w
 
 
-@pytest.mark.parametrize("scheme,limiter", [("lf", "minmod"), ("mmc", "vanleer")])
+@pytest.mark.parametrize("scheme,limiter", [("lf", "minmod"), ("mmc", "vanleer"), ("weno", "minmod")])
 def test_glm_conserves_on_periodic_grid(orc, scheme, limiter):
     """Plain GLM (EGLM sources off): mass, momentum, energy and B totals are
     conserved to rounding on a periodic grid; mean psi decays by c_d per step."""
