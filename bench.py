@@ -8,6 +8,8 @@ graph.  A step = cfl_dt + step + reflux + restriction + ghost fill over all
 leaves.  value = leaf cell-updates per second (inputs resident in HBM).
 
 Also reported on the same workload and initial data:
+  * whole WENO + TVD Runge-Kutta 2 cycles (Sec. 3.3), their rate and the
+    time of one two-stage update;
   * the FP64 path launched once per block ("plain"), its rate and the
     relative L1 distance of the FP32 result from it after the same steps;
   * roofline of the dominant kernel (the step kernel), timed with HIP events
@@ -75,6 +77,18 @@ def step_bytes_per_launch(wl, nleaves, word):
 # 746, two faces 296, update 54, sources 26, damping 1.
 FLOPS_PER_CELL = {(3, True): 1860, (3, False): 1785, (2, True): 1123 + 60, (2, False): 1123}
 
+# FP operations of one WENO stage per leaf cell-update, counted the same way
+# (Sec. 3.3): per cell, dimension and variable the two WENO face states cost
+# 30 (differences 2, smoothness 4, squares 2, each state 11 with one
+# division), primitives of the six face states 168 -> 978 in 3-D; the ring
+# of cells outside the interior needs one face state each (30 x 9 + 28 =
+# 298 for 1536 ring cells per 4096); faces 444, update 81, EGLM sources 33,
+# resistivity 75; stage 2 adds the Runge-Kutta average (18) and the psi
+# damping (1).  2-D: 540 + 112 = 652, ring 64 x 298 / 256, faces 296,
+# update 54, sources 26, resistivity 60.
+WENO_FLOPS_PER_CELL = {(3, True): (1723, 1742), (3, False): (1648, 1667),
+                       (2, True): (1163, 1182), (2, False): (1103, 1122)}
+
 # MI355X vector peak for FP32 (non-packed) and FP64: 256 CUs x 4 SIMDs x
 # 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s
 ALU_PEAK_TFLOPS = 78.6
@@ -83,7 +97,7 @@ ALU_PEAK_TFLOPS = 78.6
 def step_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_step_lf.hip", "k_step_lf3.hip", "step_common.hpp", "tile.hpp", "physics.hpp",
+    for f in ("k_step2.hip", "k_step3.hip", "step_common.hpp", "tile.hpp", "physics.hpp",
               "kernels.hpp", "map_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1204_5849_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
@@ -221,6 +235,51 @@ def time_regrid(sim, wl):
     return out
 
 
+def time_weno(wl, precision, steps, word):
+    """Whole WENO cycles (two stages, the boundary procedure on the stage,
+    reflux, restriction, fill) on the same blocks and initial data, captured
+    in a HIP graph, and map_step alone (both stages with the stage's
+    restriction and fill) timed with HIP events on its stream."""
+    import dataclasses
+    import torch
+    from paper_1204_5849_amd import native as N
+    from paper_1204_5849_amd.sim import Simulation
+    ww = dataclasses.replace(wl, scheme="weno")
+    sim = Simulation(ww, precision=precision)
+    sim.load_initial()
+    sim.autotune()
+    sim.graph_run(2)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.graph_run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    st, cnt = sim.flags()
+    sim.cfl()
+    out = torch.empty_like(sim.U)
+    torch.cuda.synchronize()
+    N.map_step(sim.ctx, sim.U, out, sim.dt, sim.sp)  # warm
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    for _ in range(5):
+        N.map_step(sim.ctx, sim.U, out, sim.dt, sim.sp)
+    e1.record(sim.stream)
+    e1.synchronize()
+    t_step = e0.elapsed_time(e1) / 5 * 1e-3
+    cells = ww.n_leaf_cells()
+    f1, f2 = WENO_FLOPS_PER_CELL[(ww.ndim, ww.eta > 0)]
+    out_d = {"ms_per_step": el / steps * 1e3, "value": cells * steps / el, "unit": "cell-updates/s",
+             "steps": steps, "step_ms": t_step * 1e3, "flags": [int(c) for c in cnt],
+             "flops_per_cell_update_stages": [f1, f2],
+             "note": "stage kernels k_step3/k_step2 <..., 1|2, 0>; per-stage durations in the "
+                     "kernel-trace summary"}
+    del out, sim
+    torch.cuda.empty_cache()
+    return out_d
+
+
 def rel_l1(a, b):
     return float(np.abs(a - b).mean() / max(np.abs(b).mean(), 1e-300))
 
@@ -235,6 +294,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-regrid", action="store_true")
+    ap.add_argument("--no-weno", action="store_true")
+    ap.add_argument("--weno-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true", help="eager launches instead of the graph")
@@ -318,7 +379,7 @@ def main():
                    else "hipGraph, batched persistent", "grids": chosen},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
-                     "kernel": "k_step_lf3" if wl.ndim == 3 else "k_step_lf2",
+                     "kernel": "k_step3 (LF)" if wl.ndim == 3 else "k_step2 (LF)",
                      "kernel_ms": t_step * 1e3,
                      "flops_per_cell_update": fpc, "algorithmic_bytes_per_launch": bytes_step,
                      "hbm_achieved_GBs": achieved, "hbm_peak_GBs": HBM_PEAK_GBS,
@@ -337,9 +398,16 @@ def main():
             f"(+{r['created']} -{r['destroyed']}); estimate {r['estimate_ms']:.3f} ms, "
             f"tree edit {r['tree_edit_ms']:.1f} ms, remap {r['remap_ms']:.1f} ms")
 
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_weno:
+        log("WENO + TVD Runge-Kutta 2 on the same workload")
+        result["weno"] = time_weno(wl, args.precision, args.weno_steps, word)
+        r = result["weno"]
+        log(f"weno: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.3f} G cell-updates/s, "
+            f"map_step {r['step_ms']:.3f} ms")
+
     if not args.no_plain:
-        del sim
-        torch.cuda.empty_cache()
         log("FP64 plain per-block path on the same workload")
         from paper_1204_5849_amd import workloads as W  # noqa: F401
         wl64 = build_workload(args.workload, "fp64")

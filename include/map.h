@@ -46,7 +46,7 @@ enum {
 };
 
 enum { MAP_FP64 = 0, MAP_FP32_MIXED = 1 };
-enum { MAP_LF = 0, MAP_MMC = 1 };
+enum { MAP_LF = 0, MAP_MMC = 1, MAP_WENO = 2 };
 enum { MAP_MINMOD = 0, MAP_VANLEER = 1, MAP_PAPER_PHI = 2 };
 enum { MAP_GLM_PAPER = 0, MAP_GLM_FASTSPEED = 1 };
 enum { MAP_BC_PERIODIC = 0, MAP_BC_OUTFLOW = 1 };
@@ -59,8 +59,13 @@ enum { MAP_EST_VAR = 0, MAP_EST_BMAG = 1 };
  *                 inside every flux/speed evaluation; CFL speeds, dt and the
  *                 totals in FP64.
  *   scheme        MAP_LF (TVD-LF: MUSCL-Hancock predictor, Rusanov flux,
- *                 Sec. 3.2) or MAP_MMC (modified MacCormack, Sec. 3.1).
- *   limiter       LF: slope limiter; MMC: flux limiter (ratio-free form).
+ *                 Sec. 3.2), MAP_MMC (modified MacCormack, Sec. 3.1, 2-D
+ *                 only) or MAP_WENO (third-order component-wise WENO face
+ *                 states, Rusanov flux, TVD Runge-Kutta 2 in time with the
+ *                 boundary procedure applied to the intermediate stage,
+ *                 Sec. 3.3).
+ *   limiter       LF: slope limiter; MMC: flux limiter (ratio-free form);
+ *                 WENO: unused.
  *   glm_mode      MAP_GLM_PAPER: c_h = cfl dx_min/dt, psi factor glm_cd per
  *                 step; MAP_GLM_FASTSPEED: c_h = alpha_g, factor
  *                 exp(-dt c_h/glm_cr).
@@ -155,16 +160,21 @@ map_status map_prolong(map_ctx *ctx, void *U, const int32_t *slots_dev, int n, v
  * dt_dev[nsims] (device memory).  Speeds are computed in FP64. */
 map_status map_cfl_dt(map_ctx *ctx, const void *U, map_dt *dt_dev, void *stream);
 
-/* One two-step update of every leaf of every simulation (Sec. 3.1 or 3.2,
- * all directions together, Sec. 3.7) with EGLM sources, resistivity and
- * psi damping, writing the interiors of the leaves of U_out.  Ghost cells
- * are read where map_fill_ghosts would copy them from (Sec. 4.3): the
- * interiors of same-level blocks in U_in (leaves, and parents holding the
- * restriction of their children) and the block's own prolongated ghosts, so
- * U_in needs up-to-date interiors and prolongated ghost regions only.
- * U_out must not overlap U_in (MAP_EINVAL): blocks read their neighbours'
- * old interiors while others are written.  Also stores the fluxes of faces
- * shared with leaves of another level, for map_reflux. */
+/* One update of every leaf of every simulation (Sec. 3.1, 3.2 or 3.3, all
+ * directions together, Sec. 3.7) with EGLM sources, resistivity and psi
+ * damping, writing the interiors of the leaves of U_out.  Ghost cells are
+ * read where map_fill_ghosts would copy them from (Sec. 4.3): the interiors
+ * of same-level blocks in U_in (leaves, and parents holding the restriction
+ * of their children) and the block's own prolongated ghosts, so U_in needs
+ * up-to-date interiors and prolongated ghost regions only.  LF and MMC:
+ * U_out must not overlap U_in (MAP_EINVAL), since blocks read their
+ * neighbours' old interiors while others are written.  WENO: both
+ * Runge-Kutta stages; the first writes the workspace's shadow state, which
+ * then gets restriction and the ghost procedure (Sec. 4.3) before the
+ * second stage reads it, and U_out may equal U_in (partial overlap is
+ * MAP_EINVAL).  U_out must not overlap the workspace.  Also stores the
+ * fluxes of faces shared with leaves of another level (for WENO the mean of
+ * both stages' fluxes), for map_reflux. */
 map_status map_step(map_ctx *ctx, const void *U_in, void *U_out, const map_dt *dt_dev,
                     void *stream);
 
@@ -187,16 +197,18 @@ map_status map_status_flags(map_ctx *ctx, uint64_t counters[4], void *stream);
  * next step reads from a block's own tile (copies into the frames of the
  * parents that feed prolongation, prolongation level by level), with dt
  * kept on the device (the record of the last step is copied to dt_dev if it
- * is not NULL).  Cycles alternate between U and the workspace's shadow
- * state; an odd nsteps ends with one device copy back into U.  On return U
+ * is not NULL).  LF and MMC cycles alternate between U and the workspace's
+ * shadow state, and an odd nsteps ends with one device copy back into U;
+ * WENO cycles update U in place (the shadow holds the stage).  On return U
  * holds the interiors of every block and its prolongated ghosts; the
  * same-level ghost regions of leaves hold unspecified values
  * (map_fill_ghosts refreshes them).  Eager launches on `stream`. */
 map_status map_advance(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
 
 /* Same cycles and result as map_advance: the pair of cycles U -> shadow ->
- * U is captured once per U into a HIP graph and replayed nsteps / 2 times on
- * `stream`; an odd nsteps adds one eager cycle and the copy back. */
+ * U (WENO: two in-place cycles) is captured once per U into a HIP graph and
+ * replayed nsteps / 2 times on `stream`; an odd nsteps adds one eager cycle
+ * (and for LF and MMC the copy back). */
 map_status map_graph_run(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
 
 /* MAP_LAUNCH_BATCHED: one launch per stage over the joint work list of all
@@ -208,8 +220,9 @@ map_status map_set_launch(map_ctx *ctx, int mode, int grid_step, int grid_fill);
 /* Time the batched step and fill launches over a set of grid sizes on U with
  * HIP events and keep the fastest (project autotuner); writes the chosen
  * sizes to chosen[2] if not NULL.  Synchronises `stream`.  The trial steps
- * write the shadow state; U's interiors are not changed (ghost frames of
- * parents that feed prolongation are rewritten with the same values). */
+ * (for WENO, first stages) write the shadow state; U's interiors are not
+ * changed (ghost frames of parents that feed prolongation are rewritten
+ * with the same values). */
 map_status map_autotune(map_ctx *ctx, void *U, int *chosen, void *stream);
 
 /* ---- regrid (Sec. 4.5) ------------------------------------------------ */

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmap.so")
-SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step_lf.hip", "k_step_lf3.hip", "k_step_mmc.hip",
+SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step2.hip", "k_step3.hip", "k_step_mmc.hip",
            "k_aux.hip", "k_regrid.hip"]
 ARCH = os.environ.get("MAP_OFFLOAD_ARCH", "gfx950")
 

@@ -141,11 +141,14 @@ map_status run_cfl(map_ctx *c, const void *U, map_dt *dt_out, hipStream_t s)
     return MAP_OK;
 }
 
-map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, hipStream_t s)
+// one launch of the block-update kernel of the scheme (for WENO: one stage)
+map_status run_step_kernel(map_ctx *c, int sch, const void *Uin, void *Uout, const void *Ubase,
+                           const map_dt *dt, hipStream_t s)
 {
     StepArgs a{};
     a.Uin = Uin;
     a.Uout = Uout;
+    a.Ubase = Ubase;
     a.blk = dptr<BlockRec>(c, c->ws.blocks);
     a.dt = dt;
     a.lvl_dx = dptr<double>(c, c->ws.lvl_dx);
@@ -162,8 +165,8 @@ map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, h
         if (c->p.scheme == MAP_MMC)
             return launch_step_mmc(c->nd, fp64(c), x, 0.0, grid, s);
         if (c->nd == 3)
-            return launch_step_lf3(fp64(c), resist, x, grid, s);
-        return launch_step_lf(c->nd, fp64(c), resist, x, grid, s);
+            return launch_step3(fp64(c), resist, sch, x, grid, s);
+        return launch_step2(fp64(c), resist, sch, x, grid, s);
     };
     const int bpw = step_blocks_per_group(c->nd, c->p.scheme);
     if (c->launch_mode == MAP_LAUNCH_PER_BLOCK) {
@@ -180,6 +183,27 @@ map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, h
         HIPCHK(launch(a, c->grid_step));
     }
     return MAP_OK;
+}
+
+void *shadow(map_ctx *c);
+
+// one update of every leaf from Uin to Uout.  WENO (Sec. 3.3): stage 1 into
+// the shadow state, restriction and the ghosts the next stage reads from a
+// block's own tile on it, stage 2 from the shadow with u^n = Uin; Uout may
+// be Uin (stage 2 reads u^n only at the cell it writes)
+map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, hipStream_t s)
+{
+    if (c->p.scheme != MAP_WENO)
+        return run_step_kernel(c, SCH_LF, Uin, Uout, nullptr, dt, s);
+    map_status st;
+    void *S1 = shadow(c);
+    if ((st = run_step_kernel(c, SCH_WENO1, Uin, S1, nullptr, dt, s)) != MAP_OK)
+        return st;
+    if ((st = run_restrict(c, S1, s)) != MAP_OK)
+        return st;
+    if ((st = run_fill(c, S1, s, false)) != MAP_OK)
+        return st;
+    return run_step_kernel(c, SCH_WENO2, S1, Uout, Uin, dt, s);
 }
 
 map_status run_reflux(map_ctx *c, void *U, const map_dt *dt, hipStream_t s)
@@ -222,10 +246,17 @@ size_t state_bytes(const map_ctx *c) { return (size_t)c->nslots * NV * c->tile *
 void *shadow(map_ctx *c) { return c->wsp + c->ws.shadow; }
 
 // n cycles alternating between U and the workspace's shadow state; an odd
-// count ends with one copy of the shadow back into U
+// count ends with one copy of the shadow back into U.  WENO cycles run in
+// place (the shadow holds the Runge-Kutta stage).
 map_status run_cycles(map_ctx *c, void *U, int n, hipStream_t s)
 {
     map_status st;
+    if (c->p.scheme == MAP_WENO) {
+        for (int i = 0; i < n; i++)
+            if ((st = run_cycle(c, U, U, s)) != MAP_OK)
+                return st;
+        return MAP_OK;
+    }
     void *S2 = shadow(c);
     for (int i = 0; i < n; i++) {
         const bool even = (i & 1) == 0;
@@ -428,8 +459,12 @@ map_status map_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt_de
     {
         const char *i0 = static_cast<const char *>(Uin), *o0 = static_cast<const char *>(Uout);
         const size_t nb = state_bytes(c);
-        if (i0 < o0 + nb && o0 < i0 + nb)
+        const bool same = c->p.scheme == MAP_WENO && i0 == o0;
+        if (!same && i0 < o0 + nb && o0 < i0 + nb)
             return fail(MAP_EINVAL, "Uout overlaps Uin (the update reads neighbour cells of Uin)");
+        const char *w0 = c->wsp;
+        if (o0 < w0 + c->ws.total && w0 < o0 + nb)
+            return fail(MAP_EINVAL, "Uout overlaps the bound workspace");
     }
     return run_step(c, Uin, Uout, dt_dev, S(stream));
 }
@@ -519,11 +554,12 @@ map_status map_graph_run(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *
             c->cap_stream = cs;
         }
         hipStream_t cs = S(c->cap_stream);
-        // two cycles, U -> shadow -> U
+        // two cycles, U -> shadow -> U (WENO: U -> U twice)
+        void *mid = c->p.scheme == MAP_WENO ? U : shadow(c);
         HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-        st = run_cycle(c, U, shadow(c), cs);
+        st = run_cycle(c, U, mid, cs);
         if (st == MAP_OK)
-            st = run_cycle(c, shadow(c), U, cs);
+            st = run_cycle(c, mid, U, cs);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(cs, &g);
         if (st != MAP_OK) {
@@ -610,7 +646,8 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
     float best_t = 1e30f;
     for (int g : cands) {
         c->grid_step = g;
-        float t = time_it([&] { return run_step(c, U, shadow(c), dt, s); });
+        const int sch = c->p.scheme == MAP_WENO ? SCH_WENO1 : SCH_LF;
+        float t = time_it([&] { return run_step_kernel(c, sch, U, shadow(c), nullptr, dt, s); });
         if (t < best_t) {
             best_t = t;
             best_step = g;

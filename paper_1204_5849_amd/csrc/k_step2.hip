@@ -1,7 +1,8 @@
-// k_step_lf.hip -- the TVD-LF block update (paper Sec. 3.2, both directions
-// together as in Sec. 3.7) with the EGLM source terms (Sec. 2), uniform
-// resistivity (Sec. 3.5) and exact psi damping, for 2-D leaf blocks (the
-// 3-D kernel is in k_step_lf3.hip).
+// k_step2.hip -- the block update of 2-D leaf blocks: the TVD-LF step
+// (paper Sec. 3.2) or one stage of WENO with TVD Runge-Kutta 2 (Sec. 3.3),
+// both directions together (Sec. 3.7), with the EGLM source terms (Sec. 2),
+// uniform resistivity (Sec. 3.5) and exact psi damping (the 3-D kernel is in
+// k_step3.hip).
 //
 // Layout and schedule (gfx950): a workgroup of 256 threads holds 14 blocks,
 // 18 columns each (x = -1 .. 16: the interior and the cell on each side
@@ -18,7 +19,11 @@
 //     fills same-level ghosts before the update and U_out must not alias
 //     U_in;
 //   * each face flux is evaluated once; the next row is prefetched from HBM
-//     while the current one is processed.
+//     while the current one is processed;
+//   * WENO stages take three-cell WENO face states (no predictor); stage 1
+//     stores u1 without damping, stage 2 stores (u + u1 + dt L(u1)) / 2, u
+//     read from U_base at the cell itself, damps psi, and averages the reflux
+//     face fluxes of both stages.
 // A persistent grid strides over the leaf list.
 #include <type_traits>
 
@@ -39,8 +44,8 @@ constexpr int NCOL2 = NB + 2;      // computing columns per block
 constexpr int NXT2 = 2 * BPW2;     // load-only cells (x = -2, x = 17) per row
 }  // namespace
 
-template <typename T, bool MIXED, bool RESIST, int LIM>
-__global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM>
+__global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
 {
     constexpr int XS = XS2, BPW = BPW2, P = P2, FC = NB;
     constexpr int SUB = BPW * NV * XS;
@@ -80,6 +85,14 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
     const T *Uin = (const T *)a.Uin;
     T *Uout = (T *)a.Uout;
     T *fbuf = (T *)a.fbuf;
+    // a reflux face flux: the step's own, or for the second WENO stage the
+    // mean with the first stage's
+    auto put_flux = [&](size_t i, T f) {
+        if constexpr (SCH == SCH_WENO2)
+            fbuf[i] = T(0.5) * fbuf[i] + T(0.5) * f;
+        else
+            fbuf[i] = f;
+    };
 
     // neighbouring blocks on one XCD, so that the ghost cells read from
     // neighbours come from that XCD's L2
@@ -202,6 +215,16 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
                 load(upp, k + 2);
             if (k + 1 <= NB + 1)
                 load_x(xc, k + 1);
+            // WENO stage 2: u of the cell finalised in this iteration
+            T ubase[SCH == SCH_WENO2 ? NV : 1];
+            if constexpr (SCH == SCH_WENO2) {
+                if (inI && k >= 1 && has) {
+                    const T *b = (const T *)a.Ubase + (size_t)slot * NV * P + (k - 1 + NG) * XS + q;
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        ubase[v] = b[v * P];
+                }
+            }
             __syncthreads();
 
             T Lin[NV], pLin = T(1), Lm[NV], Rm[NV];
@@ -213,60 +236,67 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
             if (work) {
                 // slopes from the old-time differences (limiter1)
                 T dl[2][NV];
+                T ut[NV];
+                if constexpr (SCH == SCH_LF) {
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
-                    const T *row = sc + (lb * NV + v) * XS;
-                    dl[0][v] = limiter<LIM>(u0[v] - row[q - 1], row[q + 1] - u0[v]);
-                    dl[1][v] = limiter<LIM>(u0[v] - um(v), up[v] - u0[v]);
-                }
-                // half-step predictor u~ = u - dt/(2dx) sum_d [f(u + D/2) - f(u - D/2)],
-                // evaluated optimistically; if any face state of the cell has
-                // rho <= 0 or p <= 0 the slopes fall back to zero and u~ = u
-                T acc[NV];
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    acc[v] = T(0);
-                bool ok = true;
-                auto pred = [&](auto dc) {
-                    constexpr int d = decltype(dc)::value;
-                    T s1[NV], f1[NV], f2[NV];
-                    Prim<T> w;
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        s1[v] = u0[v] + T(0.5) * dl[d][v];
-                    prim_of(ph, s1, w);
-                    ok = ok && admissible_w(s1, w);
-                    flux_w<d>(s1, w, ch2, f1);
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        s1[v] = u0[v] - T(0.5) * dl[d][v];
-                    prim_of(ph, s1, w);
-                    ok = ok && admissible_w(s1, w);
-                    flux_w<d>(s1, w, ch2, f2);
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        acc[v] += hdt[d] * (f1[v] - f2[v]);
-                };
-                pred(std::integral_constant<int, 0>{});
-                pred(std::integral_constant<int, 1>{});
-                if (!ok) {
-#pragma unroll
-                    for (int d = 0; d < 2; d++)
-#pragma unroll
-                        for (int v = 0; v < NV; v++)
-                            dl[d][v] = T(0);
+                    for (int v = 0; v < NV; v++) {
+                        const T *row = sc + (lb * NV + v) * XS;
+                        dl[0][v] = limiter<LIM>(u0[v] - row[q - 1], row[q + 1] - u0[v]);
+                        dl[1][v] = limiter<LIM>(u0[v] - um(v), up[v] - u0[v]);
+                    }
+                    // half-step predictor u~ = u - dt/(2dx) sum_d [f(u + D/2) - f(u - D/2)],
+                    // evaluated optimistically; if any face state of the cell has
+                    // rho <= 0 or p <= 0 the slopes fall back to zero and u~ = u
+                    T acc[NV];
 #pragma unroll
                     for (int v = 0; v < NV; v++)
                         acc[v] = T(0);
-                    if (has)
-                        atomicAdd(&a.cnt[0], 1ull);
-                }
-                T ut[NV];
+                    bool ok = true;
+                    auto pred = [&](auto dc) {
+                        constexpr int d = decltype(dc)::value;
+                        T s1[NV], f1[NV], f2[NV];
+                        Prim<T> w;
 #pragma unroll
-                for (int v = 0; v < NV; v++)
-                    ut[v] = u0[v] - acc[v];
-                // face states with the old-time slopes (limiter2); a state with
-                // rho <= 0 or p <= 0 is replaced by the cell's u~
+                        for (int v = 0; v < NV; v++)
+                            s1[v] = u0[v] + T(0.5) * dl[d][v];
+                        prim_of(ph, s1, w);
+                        ok = ok && admissible_w(s1, w);
+                        flux_w<d>(s1, w, ch2, f1);
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            s1[v] = u0[v] - T(0.5) * dl[d][v];
+                        prim_of(ph, s1, w);
+                        ok = ok && admissible_w(s1, w);
+                        flux_w<d>(s1, w, ch2, f2);
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            acc[v] += hdt[d] * (f1[v] - f2[v]);
+                    };
+                    pred(std::integral_constant<int, 0>{});
+                    pred(std::integral_constant<int, 1>{});
+                    if (!ok) {
+#pragma unroll
+                        for (int d = 0; d < 2; d++)
+#pragma unroll
+                            for (int v = 0; v < NV; v++)
+                                dl[d][v] = T(0);
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            acc[v] = T(0);
+                        if (has)
+                            atomicAdd(&a.cnt[0], 1ull);
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        ut[v] = u0[v] - acc[v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        ut[v] = u0[v];  // the fall-back state of WENO faces
+                }
+                // face states with the old-time slopes (limiter2) or WENO; a
+                // state with rho <= 0 or p <= 0 is replaced by the cell's u~
+                // (LF) or u (WENO)
                 const int qc[2] = {qx, k};
 #pragma unroll
                 for (int d = 0; d < 2; d++) {
@@ -274,8 +304,14 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
                     Prim<T> wl, wr;
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
-                        L[v] = ut[v] + T(0.5) * dl[d][v];
-                        R[v] = ut[v] - T(0.5) * dl[d][v];
+                        if constexpr (SCH == SCH_LF) {
+                            L[v] = ut[v] + T(0.5) * dl[d][v];
+                            R[v] = ut[v] - T(0.5) * dl[d][v];
+                        } else {
+                            const T *row = sc + (lb * NV + v) * XS;
+                            weno_pair(d == 0 ? row[q - 1] : um(v), u0[v], d == 0 ? row[q + 1] : up[v],
+                                      L[v], R[v]);
+                        }
                     }
                     prim_of(ph, L, wl);
                     prim_of(ph, R, wr);
@@ -389,7 +425,7 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
                     if (fb >= 0) {
 #pragma unroll
                         for (int v = 0; v < NV; v++)
-                            fbuf[((size_t)fb * NV + v) * FC + k] = fin[v];
+                            put_flux(((size_t)fb * NV + v) * FC + k, fin[v]);
                     }
                 }
                 if (dom && (k == 0 || k == NB)) {
@@ -397,14 +433,15 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
                     if (fb >= 0) {
 #pragma unroll
                         for (int v = 0; v < NV; v++)
-                            fbuf[((size_t)fb * NV + v) * FC + qx] = fmc[v];
+                            put_flux(((size_t)fb * NV + v) * FC + qx, fmc[v]);
                     }
                 }
             }
             __syncthreads();  // (D) x face fluxes published
 
             // ---- finalise row k-1 with the face k-1/2: y flux difference,
-            //      y resistive terms, psi damping (MHD-5 integrated exactly)
+            //      y resistive terms, the Runge-Kutta average (WENO stage 2),
+            //      psi damping (MHD-5 integrated exactly, once per step)
             if (dom && k >= 1 && has) {
                 T o[NV];
 #pragma unroll
@@ -415,7 +452,13 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
                     o[BZ] = o[BZ] + dt * ((jc[0] - jm2[0]) * i2d[1]);
                     o[EN] = o[EN] + dt * ((jc[2] - jm2[2]) * i2d[1]);
                 }
-                o[PSI] = o[PSI] * damp;
+                if constexpr (SCH == SCH_WENO2) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        o[v] = T(0.5) * (ubase[v] + o[v]);
+                }
+                if constexpr (SCH != SCH_WENO1)
+                    o[PSI] = o[PSI] * damp;
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ob[v * P + (k - 1 + NG) * XS + q] = o[v];
@@ -459,24 +502,29 @@ __global__ void __launch_bounds__(NT2) k_step_lf2(StepArgs a)
     }
 }
 
-template <typename T, bool MIXED, bool RESIST, int LIM>
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM>
 static hipError_t launch2(const StepArgs &a, int grid, hipStream_t s)
 {
     const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
-    hipLaunchKernelGGL((k_step_lf2<T, MIXED, RESIST, LIM>), dim3(g), dim3(NT2), 0, s, a);
+    hipLaunchKernelGGL((k_step2<T, MIXED, RESIST, SCH, LIM>), dim3(g), dim3(NT2), 0, s, a);
     return hipGetLastError();
 }
 
+// LF: one instance per limiter; WENO stages use no limiter
 template <typename T, bool MIXED, bool RESIST>
-static hipError_t launch2_lim(const StepArgs &a, int grid, hipStream_t s)
+static hipError_t launch2_sch(int sch, const StepArgs &a, int grid, hipStream_t s)
 {
     if (a.nitems <= 0)
         return hipSuccess;
+    if (sch == SCH_WENO1)
+        return launch2<T, MIXED, RESIST, SCH_WENO1, MAP_MINMOD>(a, grid, s);
+    if (sch == SCH_WENO2)
+        return launch2<T, MIXED, RESIST, SCH_WENO2, MAP_MINMOD>(a, grid, s);
     if (a.limiter == MAP_MINMOD)
-        return launch2<T, MIXED, RESIST, MAP_MINMOD>(a, grid, s);
+        return launch2<T, MIXED, RESIST, SCH_LF, MAP_MINMOD>(a, grid, s);
     if (a.limiter == MAP_VANLEER)
-        return launch2<T, MIXED, RESIST, MAP_VANLEER>(a, grid, s);
-    return launch2<T, MIXED, RESIST, MAP_PAPER_PHI>(a, grid, s);
+        return launch2<T, MIXED, RESIST, SCH_LF, MAP_VANLEER>(a, grid, s);
+    return launch2<T, MIXED, RESIST, SCH_LF, MAP_PAPER_PHI>(a, grid, s);
 }
 
 int step_blocks_per_group(int ndim, int scheme)
@@ -486,16 +534,13 @@ int step_blocks_per_group(int ndim, int scheme)
     return BPW2;
 }
 
-hipError_t launch_step_lf(int ndim, bool fp64, bool resist, const StepArgs &a, int grid,
-                          hipStream_t s)
+hipError_t launch_step2(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s)
 {
-    if (ndim == 3)
-        return launch_step_lf3(fp64, resist, a, grid, s);
     if (fp64)
-        return resist ? launch2_lim<double, false, true>(a, grid, s)
-                      : launch2_lim<double, false, false>(a, grid, s);
-    return resist ? launch2_lim<float, true, true>(a, grid, s)
-                  : launch2_lim<float, true, false>(a, grid, s);
+        return resist ? launch2_sch<double, false, true>(sch, a, grid, s)
+                      : launch2_sch<double, false, false>(sch, a, grid, s);
+    return resist ? launch2_sch<float, true, true>(sch, a, grid, s)
+                  : launch2_sch<float, true, false>(sch, a, grid, s);
 }
 
 }  // namespace mapk

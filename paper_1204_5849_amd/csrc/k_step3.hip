@@ -1,6 +1,7 @@
-// k_step_lf3.hip -- the TVD-LF block update (paper Sec. 3.2, all directions
-// together as in Sec. 3.7) with the EGLM source terms (Sec. 2), uniform
-// resistivity (Sec. 3.5) and exact psi damping, for 3-D leaf blocks.
+// k_step3.hip -- the block update of 3-D leaf blocks: the TVD-LF step
+// (paper Sec. 3.2) or one stage of WENO with TVD Runge-Kutta 2 (Sec. 3.3),
+// all directions together (Sec. 3.7), with the EGLM source terms (Sec. 2),
+// uniform resistivity (Sec. 3.5) and exact psi damping.
 //
 // Schedule (gfx950): one block per workgroup of 4 waves, so that two
 // workgroups share a compute unit (the FP32 kernel keeps to 256 registers
@@ -14,9 +15,9 @@
 //   * the ring of cells just outside the interior (minus its corners) feeds
 //     the block's boundary faces: lanes 0-15 of wave w own the ring side w
 //     (x = -1, x = 16, y = -1, y = 16), load its cells two planes ahead
-//     through a small LDS buffer, and run a reduced pass over them -- the
-//     predictor, the one face state the interior reads, and, on the -1 sides,
-//     the flux of that face;
+//     through a small LDS buffer, and run a reduced pass over them -- for LF
+//     the predictor, then the one face state the interior reads, and, on the
+//     -1 sides, the flux of that face;
 //   * lanes 16-35 of each wave load the remaining cells of the padded plane
 //     (outer ring and ring corners), one plane ahead;
 //   * interior columns read their planes from the block itself or, for the
@@ -24,7 +25,12 @@
 //     ring and outer cells read where their ghost descriptors point (Sec.
 //     4.3), so U_out must not alias U_in;
 //   * each face flux is evaluated once and the march-axis flux difference is
-//     formed explicitly, so a uniform state stays exactly uniform.
+//     formed explicitly, so a uniform state stays exactly uniform;
+//   * WENO stages differ only in the face states (three-cell WENO along
+//     each dimension, no predictor) and in the end of the update: stage 1
+//     stores u1 without damping, stage 2 stores (u + u1 + dt L(u1)) / 2, u
+//     read from U_base at the cell itself, then damps psi, and the reflux
+//     face fluxes become the mean of both stages' fluxes.
 // A persistent grid strides over the leaf list.
 #include <type_traits>
 
@@ -47,8 +53,8 @@ constexpr int OPW = NOUT / 4;         // outer cells per wave (20)
 static_assert(NB == 16 && NT3 == 256, "lane layout assumes 16^3 blocks");
 }  // namespace
 
-template <typename T, bool MIXED, bool RESIST, int LIM>
-__global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepArgs a)
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM>
+__global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs a)
 {
     constexpr int SY = PD;
     constexpr int SUB = NV * XS3;
@@ -110,6 +116,14 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
     T *Uout = (T *)a.Uout;
     T *fbuf = (T *)a.fbuf;
     constexpr int FC = NB * NB;
+    // a reflux face flux: the step's own, or for the second WENO stage the
+    // mean with the first stage's
+    auto put_flux = [&](size_t i, T f) {
+        if constexpr (SCH == SCH_WENO2)
+            fbuf[i] = T(0.5) * fbuf[i] + T(0.5) * f;
+        else
+            fbuf[i] = f;
+    };
 
     // neighbouring blocks on one XCD, so that the ghost cells read from
     // neighbours come from that XCD's L2
@@ -314,6 +328,16 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
             }
             if (k + 2 <= NB + 1)
                 load(upp, k + 2);
+            // WENO stage 2: u of the cell finalised in this iteration
+            T ubase[SCH == SCH_WENO2 ? NV : 1];
+            if constexpr (SCH == SCH_WENO2) {
+                if (k >= 1) {
+                    const T *b = (const T *)a.Ubase + (size_t)slot * NV * P3 + (k - 1 + NG) * XS3 + q;
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        ubase[v] = b[v * P3];
+                }
+            }
             __syncthreads();
 
             // ---- ring pass: the one face state of each ring cell the
@@ -327,18 +351,30 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
                     urm[v] = sm[v * XS3 + xq];
                     urp[v] = rn[v * NRING + ri];
                 }
-                T dl[3][NV], ut[NV];
-                slopes(sc, xq, ur, urm, urp, dl);
-                predict(ur, dl, ut);
                 // left state of the face -1/2 (ring at -1) or right state of
                 // the face NB-1/2 (ring at NB); a state with rho <= 0 or
-                // p <= 0 is replaced by the cell's u~
-                T S[NV];
+                // p <= 0 is replaced by the cell's u~ (LF) or u (WENO)
+                T S[NV], ut[NV];
                 Prim<T> ws;
+                if constexpr (SCH == SCH_LF) {
+                    T dl[3][NV];
+                    slopes(sc, xq, ur, urm, urp, dl);
+                    predict(ur, dl, ut);
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
-                    const T dv = rdim == 0 ? dl[0][v] : dl[1][v];
-                    S[v] = rlo ? ut[v] + T(0.5) * dv : ut[v] - T(0.5) * dv;
+                    for (int v = 0; v < NV; v++) {
+                        const T dv = rdim == 0 ? dl[0][v] : dl[1][v];
+                        S[v] = rlo ? ut[v] + T(0.5) * dv : ut[v] - T(0.5) * dv;
+                    }
+                } else {
+                    const int st = rdim == 0 ? 1 : SY;
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        const T *row = sc + v * XS3;
+                        T L, R;
+                        weno_pair(row[xq - st], ur[v], row[xq + st], L, R);
+                        S[v] = rlo ? L : R;
+                        ut[v] = ur[v];
+                    }
                 }
                 prim_of(ph, S, ws);
                 if (!admissible_w(S, ws)) {
@@ -374,8 +410,14 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     um[v] = sm[v * XS3 + q];
-                slopes(sc, q, u0, um, up, dl);
-                predict(u0, dl, ut);
+                if constexpr (SCH == SCH_LF) {
+                    slopes(sc, q, u0, um, up, dl);
+                    predict(u0, dl, ut);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        ut[v] = u0[v];  // the fall-back state of WENO faces
+                }
                 const int qc[3] = {qx, qy, k};
 #pragma unroll
                 for (int d = 0; d < 3; d++) {
@@ -383,8 +425,15 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
                     Prim<T> wl, wr;
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
-                        L[v] = ut[v] + T(0.5) * dl[d][v];
-                        R[v] = ut[v] - T(0.5) * dl[d][v];
+                        if constexpr (SCH == SCH_LF) {
+                            L[v] = ut[v] + T(0.5) * dl[d][v];
+                            R[v] = ut[v] - T(0.5) * dl[d][v];
+                        } else {
+                            const T *row = sc + v * XS3;
+                            const T m = d == 0 ? row[q - 1] : (d == 1 ? row[q - SY] : um[v]);
+                            const T p = d == 0 ? row[q + 1] : (d == 1 ? row[q + SY] : up[v]);
+                            weno_pair(m, u0[v], p, L[v], R[v]);
+                        }
                     }
                     prim_of(ph, L, wl);
                     prim_of(ph, R, wr);
@@ -493,7 +542,7 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
                     const int tt = (rdim == 0 ? ey : ex) + NB * k;
 #pragma unroll
                     for (int v = 0; v < NV; v++)
-                        fbuf[((size_t)fb * NV + v) * FC + tt] = f[v];
+                        put_flux(((size_t)fb * NV + v) * FC + tt, f[v]);
                 }
             }
             if constexpr (RESIST) {
@@ -530,7 +579,7 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
                     const int tt = (d == 0 ? qy : qx) + NB * k;
 #pragma unroll
                     for (int v = 0; v < NV; v++)
-                        fbuf[((size_t)fb * NV + v) * FC + tt] = fin[d][v];
+                        put_flux(((size_t)fb * NV + v) * FC + tt, fin[d][v]);
                 }
             }
             if (dom && (k == 0 || k == NB)) {
@@ -539,13 +588,14 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
                     const int tt = qx + NB * qy;
 #pragma unroll
                     for (int v = 0; v < NV; v++)
-                        fbuf[((size_t)fb * NV + v) * FC + tt] = fmc[v];
+                        put_flux(((size_t)fb * NV + v) * FC + tt, fmc[v]);
                 }
             }
             __syncthreads();  // (D) in-plane face fluxes published
 
             // ---- finalise plane k-1 with the face k-1/2: z flux difference,
-            //      z resistive terms, psi damping (MHD-5 integrated exactly)
+            //      z resistive terms, the Runge-Kutta average (WENO stage 2),
+            //      psi damping (MHD-5 integrated exactly, once per step)
             if (dom && k >= 1) {
                 T o[NV];
 #pragma unroll
@@ -556,7 +606,13 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
                     o[BY] = o[BY] - dt * ((jc[0] - jm2[0]) * i2d[2]);
                     o[EN] = o[EN] + dt * ((jc[2] - jm2[2]) * i2d[2]);
                 }
-                o[PSI] = o[PSI] * damp;
+                if constexpr (SCH == SCH_WENO2) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        o[v] = T(0.5) * (ubase[v] + o[v]);
+                }
+                if constexpr (SCH != SCH_WENO1)
+                    o[PSI] = o[PSI] * damp;
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ob[v * P3 + (k - 1 + NG) * XS3 + q] = o[v];
@@ -602,33 +658,38 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step_lf3(StepAr
     }
 }
 
-template <typename T, bool MIXED, bool RESIST, int LIM>
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM>
 static hipError_t launch3(const StepArgs &a, int grid, hipStream_t s)
 {
     const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
-    hipLaunchKernelGGL((k_step_lf3<T, MIXED, RESIST, LIM>), dim3(g), dim3(NT3), 0, s, a);
+    hipLaunchKernelGGL((k_step3<T, MIXED, RESIST, SCH, LIM>), dim3(g), dim3(NT3), 0, s, a);
     return hipGetLastError();
 }
 
+// LF: one instance per limiter; WENO stages use no limiter
 template <typename T, bool MIXED, bool RESIST>
-static hipError_t launch3_lim(const StepArgs &a, int grid, hipStream_t s)
+static hipError_t launch3_sch(int sch, const StepArgs &a, int grid, hipStream_t s)
 {
     if (a.nitems <= 0)
         return hipSuccess;
+    if (sch == SCH_WENO1)
+        return launch3<T, MIXED, RESIST, SCH_WENO1, MAP_MINMOD>(a, grid, s);
+    if (sch == SCH_WENO2)
+        return launch3<T, MIXED, RESIST, SCH_WENO2, MAP_MINMOD>(a, grid, s);
     if (a.limiter == MAP_MINMOD)
-        return launch3<T, MIXED, RESIST, MAP_MINMOD>(a, grid, s);
+        return launch3<T, MIXED, RESIST, SCH_LF, MAP_MINMOD>(a, grid, s);
     if (a.limiter == MAP_VANLEER)
-        return launch3<T, MIXED, RESIST, MAP_VANLEER>(a, grid, s);
-    return launch3<T, MIXED, RESIST, MAP_PAPER_PHI>(a, grid, s);
+        return launch3<T, MIXED, RESIST, SCH_LF, MAP_VANLEER>(a, grid, s);
+    return launch3<T, MIXED, RESIST, SCH_LF, MAP_PAPER_PHI>(a, grid, s);
 }
 
-hipError_t launch_step_lf3(bool fp64, bool resist, const StepArgs &a, int grid, hipStream_t s)
+hipError_t launch_step3(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s)
 {
     if (fp64)
-        return resist ? launch3_lim<double, false, true>(a, grid, s)
-                      : launch3_lim<double, false, false>(a, grid, s);
-    return resist ? launch3_lim<float, true, true>(a, grid, s)
-                  : launch3_lim<float, true, false>(a, grid, s);
+        return resist ? launch3_sch<double, false, true>(sch, a, grid, s)
+                      : launch3_sch<double, false, false>(sch, a, grid, s);
+    return resist ? launch3_sch<float, true, true>(sch, a, grid, s)
+                  : launch3_sch<float, true, false>(sch, a, grid, s);
 }
 
 }  // namespace mapk

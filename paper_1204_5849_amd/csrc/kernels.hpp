@@ -7,9 +7,16 @@
 
 namespace mapk {
 
+// what one launch of a block-update kernel computes: the TVD-LF step
+// (Sec. 3.2), or one stage of WENO with TVD Runge-Kutta 2 (Sec. 3.3):
+// stage 1 u1 = u + dt L(u); stage 2 (u + u1 + dt L(u1)) / 2 with the psi
+// damping of the whole step
+enum { SCH_LF = 0, SCH_WENO1 = 1, SCH_WENO2 = 2 };
+
 struct StepArgs {
     const void *Uin;
     void *Uout;
+    const void *Ubase;      // WENO stage 2: u^n, read at the updated cells only (may be Uout)
     const int32_t *leaves;  // leaf slots processed by this launch
     int nleaves;
     int nitems;             // work items (groups of blocks per workgroup)
@@ -101,9 +108,8 @@ struct RemapArgs {
 };
 
 // launchers (defined in the .hip files); return hipError_t of the launch
-hipError_t launch_step_lf(int ndim, bool fp64, bool resist, const StepArgs &a, int grid,
-                          hipStream_t s);
-hipError_t launch_step_lf3(bool fp64, bool resist, const StepArgs &a, int grid, hipStream_t s);
+hipError_t launch_step2(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s);
+hipError_t launch_step3(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s);
 hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double alpha_unused, int grid,
                            hipStream_t s);
 int step_blocks_per_group(int ndim, int scheme);

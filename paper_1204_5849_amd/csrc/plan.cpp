@@ -61,7 +61,7 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
         err = "unknown precision";
         return MAP_EINVAL;
     }
-    if (p->scheme != MAP_LF && p->scheme != MAP_MMC) {
+    if (p->scheme != MAP_LF && p->scheme != MAP_MMC && p->scheme != MAP_WENO) {
         err = "unknown scheme";
         return MAP_EINVAL;
     }

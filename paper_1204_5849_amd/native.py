@@ -14,14 +14,14 @@ LIB_PATH = os.path.join(PKG, "libmap.so")
 MAP_OK, MAP_EINVAL, MAP_ETREE, MAP_ENOMEM, MAP_EHIP, MAP_ENONFINITE, MAP_ENEGPRESSURE, MAP_ESTATE = \
     0, -1, -2, -3, -4, -5, -6, -7
 MAP_FP64, MAP_FP32_MIXED = 0, 1
-MAP_LF, MAP_MMC = 0, 1
+MAP_LF, MAP_MMC, MAP_WENO = 0, 1, 2
 MAP_MINMOD, MAP_VANLEER, MAP_PAPER_PHI = 0, 1, 2
 MAP_GLM_PAPER, MAP_GLM_FASTSPEED = 0, 1
 MAP_BC_PERIODIC, MAP_BC_OUTFLOW = 0, 1
 MAP_LAUNCH_BATCHED, MAP_LAUNCH_PER_BLOCK = 0, 1
 MAP_EST_VAR, MAP_EST_BMAG = 0, 1
 
-SCHEMES = {"lf": MAP_LF, "mmc": MAP_MMC}
+SCHEMES = {"lf": MAP_LF, "mmc": MAP_MMC, "weno": MAP_WENO}
 LIMITERS = {"minmod": MAP_MINMOD, "vanleer": MAP_VANLEER, "paper": MAP_PAPER_PHI}
 GLM = {"paper": MAP_GLM_PAPER, "fastspeed": MAP_GLM_FASTSPEED}
 BC = {"periodic": MAP_BC_PERIODIC, "outflow": MAP_BC_OUTFLOW}
