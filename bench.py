@@ -235,7 +235,7 @@ def time_regrid(sim, wl):
     return out
 
 
-def time_weno(wl, precision, steps, word):
+def time_weno(wl, precision, steps, autotune=True):
     """Whole WENO cycles (two stages, the boundary procedure on the stage,
     reflux, restriction, fill) on the same blocks and initial data, captured
     in a HIP graph, and map_step alone (both stages with the stage's
@@ -247,7 +247,8 @@ def time_weno(wl, precision, steps, word):
     ww = dataclasses.replace(wl, scheme="weno")
     sim = Simulation(ww, precision=precision)
     sim.load_initial()
-    sim.autotune()
+    if autotune:
+        sim.autotune()
     sim.graph_run(2)
     sim.sync()
     torch.cuda.synchronize()
@@ -402,7 +403,7 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_weno:
         log("WENO + TVD Runge-Kutta 2 on the same workload")
-        result["weno"] = time_weno(wl, args.precision, args.weno_steps, word)
+        result["weno"] = time_weno(wl, args.precision, args.weno_steps, not args.no_autotune)
         r = result["weno"]
         log(f"weno: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.3f} G cell-updates/s, "
             f"map_step {r['step_ms']:.3f} ms")

@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
             }
             __syncthreads();
 
-            T Lin[NV], pLin = T(1), Lm[NV], Rm[NV];
+            T Lin[NV], pLin = T(1), Lm[NV], Rm[NV], fmc[NV];
             T pLm = T(1), pRm = T(1);
             T src[4] = {T(0), T(0), T(0), T(0)};
             T jc[3] = {T(0), T(0), T(0)};
@@ -351,6 +351,10 @@ __global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
                         pRm = wr.p;
                     }
                 }
+                // the flux of the face k-1/2 from registers only, formed
+                // before the barriers so that its states die early
+                if (inI && k >= 0)
+                    rusanov_p<1>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
                 // EGLM sources from central differences of u^n
                 if (a.eglm && inI && kI) {
                     const T *bx = sc + (lb * NV + BX) * XS;
@@ -388,7 +392,7 @@ __global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
             }
             __syncthreads();  // (B) right face states, their pressures and eta J published
 
-            // ---- fluxes of the x faces of row k and of the face k-1/2
+            // ---- fluxes of the x faces of row k
             T fin[NV];
             T rin[3] = {T(0), T(0), T(0)};
             const bool dof = kI && lane && qx >= -1 && qx < NB;
@@ -409,9 +413,6 @@ __global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
                 }
             }
             const bool dom = inI && k >= 0;
-            T fmc[NV];
-            if (dom)
-                rusanov_p<1>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
             __syncthreads();  // (C) all reads of the right face states done
             if (dof) {
 #pragma unroll

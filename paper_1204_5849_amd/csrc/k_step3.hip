@@ -328,16 +328,6 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
             }
             if (k + 2 <= NB + 1)
                 load(upp, k + 2);
-            // WENO stage 2: u of the cell finalised in this iteration
-            T ubase[SCH == SCH_WENO2 ? NV : 1];
-            if constexpr (SCH == SCH_WENO2) {
-                if (k >= 1) {
-                    const T *b = (const T *)a.Ubase + (size_t)slot * NV * P3 + (k - 1 + NG) * XS3 + q;
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        ubase[v] = b[v * P3];
-                }
-            }
             __syncthreads();
 
             // ---- ring pass: the one face state of each ring cell the
@@ -399,7 +389,7 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
 
             // ---- interior pass: slopes, predictor, face states in the three
             //      dimensions, EGLM sources, eta J
-            T Lin[2][NV], pLin[2], Lm[NV], Rm[NV];
+            T Lin[2][NV], pLin[2], Lm[NV], Rm[NV], fmc[NV];
             T pLm = T(1), pRm = T(1);
             T src[4] = {T(0), T(0), T(0), T(0)};
             T jc[3] = {T(0), T(0), T(0)};
@@ -477,6 +467,10 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
                         pRm = wr.p;
                     }
                 }
+                // the flux of the face k-1/2 from registers only: formed here,
+                // before the barriers, so that its states die early
+                if (k >= 0)
+                    rusanov_p<2>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
                 // EGLM sources from central differences of u^n
                 if (a.eglm && kI) {
                     const T *bx = sc + BX * XS3, *by = sc + BY * XS3, *ps = sc + PSI * XS3;
@@ -504,8 +498,8 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
             }
             __syncthreads();  // (B) face states, their pressures and eta J published
 
-            // ---- fluxes: in-plane faces x+1/2, y+1/2 of the interior cells,
-            //      the faces -1/2 (ring waves of the -1 sides), and the face k-1/2
+            // ---- fluxes: in-plane faces x+1/2, y+1/2 of the interior cells and
+            //      the faces -1/2 (ring waves of the -1 sides)
             T fin[2][NV];
             T rin[4] = {T(0), T(0), T(0), T(0)};
             if (kI) {
@@ -556,10 +550,17 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
                 }
             }
             const bool dom = k >= 0;
-            T fmc[NV];
-            if (dom)
-                rusanov_p<2>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
             __syncthreads();  // (C) all reads of the face states done
+            // WENO stage 2: u of the cell finalised in this iteration
+            T ubase[SCH == SCH_WENO2 ? NV : 1];
+            if constexpr (SCH == SCH_WENO2) {
+                if (k >= 1) {
+                    const T *b = (const T *)a.Ubase + (size_t)slot * NV * P3 + (k - 1 + NG) * XS3 + q;
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        ubase[v] = b[v * P3];
+                }
+            }
             if (kI) {
 #pragma unroll
                 for (int d = 0; d < 2; d++)
