@@ -28,11 +28,13 @@ LF, MMC, WENO = 0, 1, 2
 MINMOD, VANLEER, PAPER_PHI = 0, 1, 2
 GLM_PAPER, GLM_FASTSPEED = 0, 1
 BC_PERIODIC, BC_OUTFLOW = 0, 1
+RUSANOV, HLLC = 0, 1
 
 _SCHEMES = {"lf": LF, "mmc": MMC, "weno": WENO}
 _LIMITERS = {"minmod": MINMOD, "vanleer": VANLEER, "paper": PAPER_PHI}
 _GLM = {"paper": GLM_PAPER, "fastspeed": GLM_FASTSPEED}
 _BC = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW}
+_RIEMANN = {"rusanov": RUSANOV, "hllc": HLLC}
 
 
 def build(force: bool = True) -> str:
@@ -50,7 +52,7 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("ndim", C.c_int), ("physics", C.c_int), ("scheme", C.c_int),
                 ("limiter", C.c_int), ("glm_mode", C.c_int), ("eglm_sources", C.c_int),
-                ("gamma", C.c_double), ("cfl", C.c_double), ("cd", C.c_double),
+                ("riemann", C.c_int), ("gamma", C.c_double), ("cfl", C.c_double), ("cd", C.c_double),
                 ("cr", C.c_double), ("eta", C.c_double), ("adv", C.c_double * 3)]
 
 
@@ -93,6 +95,8 @@ def lib():
         L.orc_speed.restype = C.c_double
         L.orc_limiter.argtypes = [C.c_int, C.c_double, C.c_double]
         L.orc_limiter.restype = C.c_double
+        L.orc_face_flux.argtypes = [pp, dp, dp, C.c_int, C.c_double, dp]
+        L.orc_hllc_fan.argtypes = [pp, dp, dp, C.c_int, C.c_double, dp, dp, dp]
         L.orc_weno_face.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
         L.orc_weno_face.restype = C.c_double
         L.orc_prim_to_cons.argtypes = [pp, dp, C.c_long]
@@ -139,7 +143,7 @@ def _ip(a):
 
 def make_params(ndim=2, physics=MHD, scheme="lf", limiter="minmod", glm_mode="paper",
                 eglm_sources=True, gamma=5.0 / 3.0, cfl=0.4, cd=0.18, cr=0.18, eta=0.0,
-                adv=(0.0, 0.0, 0.0)) -> Params:
+                adv=(0.0, 0.0, 0.0), riemann="rusanov") -> Params:
     p = Params()
     p.ndim = ndim
     p.physics = physics
@@ -147,6 +151,7 @@ def make_params(ndim=2, physics=MHD, scheme="lf", limiter="minmod", glm_mode="pa
     p.limiter = _LIMITERS.get(limiter, limiter)
     p.glm_mode = _GLM.get(glm_mode, glm_mode)
     p.eglm_sources = int(bool(eglm_sources))
+    p.riemann = _RIEMANN.get(riemann, riemann)
     p.gamma, p.cfl, p.cd, p.cr, p.eta = gamma, cfl, cd, cr, eta
     for i in range(3):
         p.adv[i] = adv[i]
@@ -156,7 +161,7 @@ def make_params(ndim=2, physics=MHD, scheme="lf", limiter="minmod", glm_mode="pa
 def params_from_workload(w) -> Params:
     return make_params(ndim=w.ndim, scheme=w.scheme, limiter=w.limiter, glm_mode=w.glm_mode,
                        eglm_sources=w.eglm_sources, gamma=w.gamma, cfl=w.cfl, cd=w.cd,
-                       cr=w.cr, eta=w.eta)
+                       cr=w.cr, eta=w.eta, riemann=w.riemann)
 
 
 def nvar(p: Params) -> int:
@@ -184,6 +189,24 @@ def speed(p, u, dim):
 def limiter(kind, a, b):
     kind = _LIMITERS.get(kind, kind)
     return lib().orc_limiter(kind, float(a), float(b))
+
+
+def face_flux(p, L, R, dim, ch=0.0):
+    """Face flux (Rusanov or HLLC, as p.riemann selects) between two states."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    out = np.zeros(nvar(p))
+    lib().orc_face_flux(C.byref(p), _dp(L), _dp(R), dim, float(ch), _dp(out))
+    return out
+
+
+def hllc_fan(p, L, R, dim, ch=0.0):
+    """HLLC fan of a face: ((S_L, S_M, S_R), star state left, star state right)."""
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    R = np.ascontiguousarray(R, dtype=np.float64)
+    S, a, b = np.zeros(3), np.zeros(9), np.zeros(9)
+    lib().orc_hllc_fan(C.byref(p), _dp(L), _dp(R), dim, float(ch), _dp(S), _dp(a), _dp(b))
+    return S, a, b
 
 
 def weno_face(um, u0, up, side):

@@ -107,6 +107,24 @@ void orc_flux(const orc_params *p, const double *u, int d, double ch, double *f)
     f[PSI] = ch * ch * Bd;
 }
 
+/* fast magnetosonic speed along d */
+static double fast_speed(const orc_params *p, const double *u, int d)
+{
+    double ir = 1.0 / u[RHO];
+    double pr = orc_pressure(p, u);
+    double a2 = p->gamma * pr * ir;
+    double bb = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
+    double b2 = bb * ir;
+    double s = a2 + b2;
+    double disc = s * s - 4.0 * a2 * (u[BX + d] * u[BX + d]) * ir;
+    if (disc < 0.0)
+        disc = 0.0;
+    double cf2 = 0.5 * (s + sqrt(disc));
+    if (cf2 < 0.0)
+        cf2 = 0.0;
+    return sqrt(cf2);
+}
+
 /* |v_d| + fast magnetosonic speed along d (the "local maximum eigenvalue"
  * of the MHD part; the GLM speed c_h is handled separately). */
 double orc_speed(const orc_params *p, const double *u, int d)
@@ -265,6 +283,167 @@ static void lf_predict(const orc_params *p, const geo *G, const double *u,
             }
 }
 
+/* Rusanov flux (Equ:LFFlux): alpha = the larger fast speed |v_d| + c_f of
+ * the two states for the MHD components, c_h for the GLM pair (B_d, psi),
+ * which makes the pair's flux Dedner's exact upwind flux of its linear
+ * system. */
+static void rusanov_flux(const orc_params *p, const double *L, const double *R, int d, double ch,
+                         double *f)
+{
+    int nv = orc_nvar(p);
+    double FL[NVMAX], FR[NVMAX];
+    orc_flux(p, L, d, ch, FL);
+    orc_flux(p, R, d, ch, FR);
+    double aL = orc_speed(p, L, d), aR = orc_speed(p, R, d);
+    double a = aL > aR ? aL : aR;
+    for (int k = 0; k < nv; k++) {
+        double al = glm_component(p, k, d) ? ch : a;
+        f[k] = 0.5 * (FL[k] + FR[k]) - 0.5 * al * (R[k] - L[k]);
+    }
+}
+
+/* HLLC flux (the paper names the HLLC solver of Gurski for MHD without
+ * printing it; this is that construction with the intermediate states of
+ * Li's HLLC for MHD), across a face normal to d:
+ *  1. The GLM pair (B_d, psi) is a linear system with speeds +-c_h; its
+ *     exact interface values are B_m = (B_dL + B_dR)/2 - (psi_R - psi_L)/(2 c_h)
+ *     and psi_m = (psi_L + psi_R)/2 - c_h (B_dR - B_dL)/2, with fluxes psi_m
+ *     and c_h^2 B_m.  (c_h = 0: B_m is the mean, the flux of B_d is the mean
+ *     of psi and that of psi is zero.)
+ *  2. Both states take B_d = B_m, so the normal field is continuous, and the
+ *     other seven components get the HLLC fan: outer speeds
+ *     S_L = min(v_L, v_R) - max(c_fL, c_fR), S_R = max(v_L, v_R) + max(c_fL, c_fR)
+ *     (v = v_d, c_f the fast speeds); the HLL mean state
+ *     U_hll = (S_R U_R - S_L U_L - F_R + F_L) / (S_R - S_L);
+ *     the contact speed S_M = (rho v_d)_hll / rho_hll; the total pressure
+ *     of the star region p* = rho_K (S_K - v_K)(S_M - v_K) + p_T,K (the
+ *     same from both sides; their mean is used); on side K the star state
+ *       rho* = rho_K (S_K - v_K) / (S_K - S_M),  (rho v_d)* = rho* S_M,
+ *       (rho v_t)* = [rho_K v_t,K (S_K - v_K) - B_m (B_t,hll - B_t,K)] / (S_K - S_M),
+ *       B_t* = B_t,hll,
+ *       e* = [e_K (S_K - v_K) - p_T,K v_K + p* S_M + B_m (v_K.B_K - v_hll.B_hll)] / (S_K - S_M),
+ *     with v_hll = (rho v)_hll / rho_hll; the flux is F_L (S_L >= 0),
+ *     F_L + S_L (U*_L - U_L) (S_L < 0 <= S_M), F_R + S_R (U*_R - U_R)
+ *     (S_M < 0 < S_R) or F_R (S_R <= 0). */
+typedef struct {
+    double Bm, psim;          /* interface values of the GLM pair */
+    double S[3];              /* S_L, S_M, S_R */
+    double U[2][NVMAX];       /* the two states with B_d = B_m */
+    double F[2][NVMAX];       /* their physical fluxes */
+    double Us[2][NVMAX];      /* star states (rho, momentum, B, e; psi unused) */
+} hllc_fan;
+
+static void hllc_fan_of(const orc_params *p, const double *L0, const double *R0, int d, double ch,
+                        hllc_fan *h)
+{
+    if (ch > 0.0) {
+        h->Bm = 0.5 * (L0[BX + d] + R0[BX + d]) - (R0[PSI] - L0[PSI]) / (2.0 * ch);
+        h->psim = 0.5 * (L0[PSI] + R0[PSI]) - 0.5 * ch * (R0[BX + d] - L0[BX + d]);
+    } else {
+        h->Bm = 0.5 * (L0[BX + d] + R0[BX + d]);
+        h->psim = 0.5 * (L0[PSI] + R0[PSI]);
+    }
+    double v[2], pt[2], cf[2], vb[2];
+    for (int s = 0; s < 2; s++) {
+        const double *u0 = s ? R0 : L0;
+        double *U = h->U[s];
+        for (int k = 0; k < 9; k++)
+            U[k] = u0[k];
+        U[BX + d] = h->Bm;
+        orc_flux(p, U, d, ch, h->F[s]);
+        double ir = 1.0 / U[RHO];
+        v[s] = U[MX + d] * ir;
+        double bb = U[BX] * U[BX] + U[BY] * U[BY] + U[BZ] * U[BZ];
+        pt[s] = orc_pressure(p, U) + 0.5 * bb;
+        cf[s] = fast_speed(p, U, d);
+        vb[s] = (U[MX] * U[BX] + U[MY] * U[BY] + U[MZ] * U[BZ]) * ir;
+    }
+    double cmax = cf[0] > cf[1] ? cf[0] : cf[1];
+    double SL = (v[0] < v[1] ? v[0] : v[1]) - cmax;
+    double SR = (v[0] > v[1] ? v[0] : v[1]) + cmax;
+    /* HLL mean state */
+    double hll[NVMAX];
+    for (int k = 0; k < 9; k++)
+        hll[k] = (SR * h->U[1][k] - SL * h->U[0][k] - h->F[1][k] + h->F[0][k]) / (SR - SL);
+    hll[BX + d] = h->Bm;
+    double vh[3];
+    for (int j = 0; j < 3; j++)
+        vh[j] = hll[MX + j] / hll[RHO];
+    double SM = vh[d];
+    double vbh = vh[0] * hll[BX] + vh[1] * hll[BY] + vh[2] * hll[BZ];
+    double ps[2];
+    for (int s = 0; s < 2; s++) {
+        double S = s ? SR : SL;
+        ps[s] = h->U[s][RHO] * (S - v[s]) * (SM - v[s]) + pt[s];
+    }
+    double pst = 0.5 * (ps[0] + ps[1]);
+    for (int s = 0; s < 2; s++) {
+        const double *U = h->U[s];
+        double *st = h->Us[s];
+        double S = s ? SR : SL;
+        double den = S - SM;
+        double sv = S - v[s];
+        st[RHO] = U[RHO] * sv / den;
+        for (int j = 0; j < 3; j++) {
+            if (j == d) {
+                st[MX + j] = st[RHO] * SM;
+                st[BX + j] = h->Bm;
+            } else {
+                st[MX + j] = (U[MX + j] * sv - h->Bm * (hll[BX + j] - U[BX + j])) / den;
+                st[BX + j] = hll[BX + j];
+            }
+        }
+        st[EN] = (U[EN] * sv - pt[s] * v[s] + pst * SM + h->Bm * (vb[s] - vbh)) / den;
+        st[PSI] = 0.0;
+    }
+    h->S[0] = SL;
+    h->S[1] = SM;
+    h->S[2] = SR;
+}
+
+static void hllc_flux(const orc_params *p, const double *L0, const double *R0, int d, double ch,
+                      double *f)
+{
+    hllc_fan h;
+    hllc_fan_of(p, L0, R0, d, ch, &h);
+    double SL = h.S[0], SM = h.S[1], SR = h.S[2];
+    if (SL >= 0.0 || SR <= 0.0) {
+        const double *F = h.F[SL >= 0.0 ? 0 : 1];
+        for (int k = 0; k < 8; k++)
+            f[k] = F[k];
+    } else {
+        int s = SM >= 0.0 ? 0 : 1;
+        double S = s ? SR : SL;
+        for (int k = 0; k < 8; k++)
+            f[k] = h.F[s][k] + S * (h.Us[s][k] - h.U[s][k]);
+    }
+    /* the GLM pair */
+    f[BX + d] = h.psim;
+    f[PSI] = ch * ch * h.Bm;
+}
+
+void orc_hllc_fan(const orc_params *p, const double *L, const double *R, int d, double ch,
+                  double S[3], double UsL[9], double UsR[9])
+{
+    hllc_fan h;
+    hllc_fan_of(p, L, R, d, ch, &h);
+    for (int k = 0; k < 3; k++)
+        S[k] = h.S[k];
+    for (int k = 0; k < 9; k++) {
+        UsL[k] = h.Us[0][k];
+        UsR[k] = h.Us[1][k];
+    }
+}
+
+void orc_face_flux(const orc_params *p, const double *L, const double *R, int d, double ch,
+                   double *f)
+{
+    if (p->physics == ORC_MHD && p->riemann == ORC_HLLC)
+        hllc_flux(p, L, R, d, ch, f);
+    else
+        rusanov_flux(p, L, R, d, ch, f);
+}
+
 /* LF corrector fluxes (limiter2 + Equ:LFFlux) on every face of dimension d
  * that bounds an interior cell; the face c+1/2 is stored at index c. */
 static void lf_faces(const orc_params *p, const geo *G, const double *ut,
@@ -279,7 +458,7 @@ static void lf_faces(const orc_params *p, const geo *G, const double *ut,
         for (int y = lo[1]; y < hi[1]; y++)
             for (int x = lo[0]; x < hi[0]; x++) {
                 long c = at(G, x, y, z), cn = c + G->s[d];
-                double L[NVMAX], R[NVMAX], FL[NVMAX], FR[NVMAX];
+                double L[NVMAX], R[NVMAX];
                 for (int k = 0; k < nv; k++) {
                     L[k] = ut[k * P + c] + 0.5 * sl[((long)d * nv + k) * P + c];
                     R[k] = ut[k * P + cn] - 0.5 * sl[((long)d * nv + k) * P + cn];
@@ -292,14 +471,10 @@ static void lf_faces(const orc_params *p, const geo *G, const double *ut,
                     load(ut, P, nv, cn, R);
                     cnt[1]++;
                 }
-                orc_flux(p, L, d, ch, FL);
-                orc_flux(p, R, d, ch, FR);
-                double aL = orc_speed(p, L, d), aR = orc_speed(p, R, d);
-                double a = aL > aR ? aL : aR;
-                for (int k = 0; k < nv; k++) {
-                    double al = glm_component(p, k, d) ? ch : a;
-                    fh[k * P + c] = 0.5 * (FL[k] + FR[k]) - 0.5 * al * (R[k] - L[k]);
-                }
+                double fc[NVMAX];
+                orc_face_flux(p, L, R, d, ch, fc);
+                for (int k = 0; k < nv; k++)
+                    fh[k * P + c] = fc[k];
             }
 }
 
@@ -351,7 +526,7 @@ static void weno_faces(const orc_params *p, const geo *G, const double *u, int d
         for (int y = lo[1]; y < hi[1]; y++)
             for (int x = lo[0]; x < hi[0]; x++) {
                 long c = at(G, x, y, z), cn = c + s;
-                double L[NVMAX], R[NVMAX], FL[NVMAX], FR[NVMAX];
+                double L[NVMAX], R[NVMAX];
                 for (int k = 0; k < nv; k++) {
                     const double *q = u + k * P;
                     L[k] = weno_minus(q[c - s], q[c], q[cn]);
@@ -365,14 +540,10 @@ static void weno_faces(const orc_params *p, const geo *G, const double *u, int d
                     load(u, P, nv, cn, R);
                     cnt[1]++;
                 }
-                orc_flux(p, L, d, ch, FL);
-                orc_flux(p, R, d, ch, FR);
-                double aL = orc_speed(p, L, d), aR = orc_speed(p, R, d);
-                double a = aL > aR ? aL : aR;
-                for (int k = 0; k < nv; k++) {
-                    double al = glm_component(p, k, d) ? ch : a;
-                    fh[k * P + c] = 0.5 * (FL[k] + FR[k]) - 0.5 * al * (R[k] - L[k]);
-                }
+                double fc[NVMAX];
+                orc_face_flux(p, L, R, d, ch, fc);
+                for (int k = 0; k < nv; k++)
+                    fh[k * P + c] = fc[k];
             }
 }
 

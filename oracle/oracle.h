@@ -27,6 +27,7 @@ enum { ORC_LF = 0, ORC_MMC = 1, ORC_WENO = 2 };
 enum { ORC_MINMOD = 0, ORC_VANLEER = 1, ORC_PAPER_PHI = 2 };
 enum { ORC_GLM_PAPER = 0, ORC_GLM_FASTSPEED = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
+enum { ORC_RUSANOV = 0, ORC_HLLC = 1 };
 
 typedef struct {
     int ndim;          /* 2 or 3 */
@@ -35,6 +36,7 @@ typedef struct {
     int limiter;       /* slope limiter (LF) or flux limiter (MMC) */
     int glm_mode;      /* how c_h and the psi damping factor follow from dt */
     int eglm_sources;  /* 1: EGLM source terms on, 0: plain GLM */
+    int riemann;       /* face flux of LF and WENO: ORC_RUSANOV or ORC_HLLC */
     double gamma, cfl, cd, cr, eta;
     double adv[3];     /* scalar physics: constant advection velocity */
 } orc_params;
@@ -60,6 +62,14 @@ void   orc_flux(const orc_params *p, const double *u, int dim, double ch,
                 double *f);
 double orc_speed(const orc_params *p, const double *u, int dim);
 double orc_limiter(int kind, double a, double b);
+/* face flux between the states L and R across a face normal to `dim`:
+ * Rusanov (Equ:LFFlux) or HLLC, as p->riemann selects */
+void   orc_face_flux(const orc_params *p, const double *L, const double *R, int dim,
+                     double ch, double *f);
+/* the HLLC fan of a face (for tests): speeds S_L, S_M, S_R and the star
+ * states of both sides, computed with B_d replaced by the GLM interface value */
+void   orc_hllc_fan(const orc_params *p, const double *L, const double *R, int dim,
+                    double ch, double S[3], double UsL[9], double UsR[9]);
 /* WENO face state (Sec. 3.3) from the cells i-1, i, i+1: side 0 gives
  * u^-_{i+1/2} (left state of the face right of cell i), side 1 gives
  * u^+_{i-1/2} (right state of the face left of cell i). */

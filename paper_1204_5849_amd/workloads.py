@@ -49,6 +49,7 @@ class Workload:
     n: int = 16
     scheme: str = "lf"
     limiter: str = "minmod"
+    riemann: str = "rusanov"        # face flux of LF and WENO: "rusanov" or "hllc"
     glm_mode: str = "paper"
     eglm_sources: bool = True
     gamma: float = 5.0 / 3.0
