@@ -8,8 +8,9 @@ graph.  A step = cfl_dt + step + reflux + restriction + ghost fill over all
 leaves.  value = leaf cell-updates per second (inputs resident in HBM).
 
 Also reported on the same workload and initial data:
-  * whole WENO + TVD Runge-Kutta 2 cycles (Sec. 3.3), their rate and the
-    time of one two-stage update;
+  * whole WENO + TVD Runge-Kutta 2 cycles (Sec. 3.3), with the Rusanov and
+    with the HLLC face flux, their rates and the time of one two-stage
+    update;
   * the FP64 path launched once per block ("plain"), its rate and the
     relative L1 distance of the FP32 result from it after the same steps;
   * roofline of the dominant kernel (the step kernel), timed with HIP events
@@ -88,6 +89,13 @@ FLOPS_PER_CELL = {(3, True): 1860, (3, False): 1785, (2, True): 1123 + 60, (2, F
 # update 54, sources 26, resistivity 60.
 WENO_FLOPS_PER_CELL = {(3, True): (1723, 1742), (3, False): (1648, 1667),
                        (2, True): (1163, 1182), (2, False): (1103, 1122)}
+
+# The HLLC face flux in place of the Rusanov one, counted the same way for a
+# face inside the fan: the GLM pair 12, per side the state with B_d = B_m
+# (primitives 9, pressure 6, flux 28, total pressure 2, fast speed 15,
+# v.B 5) 65, outer speeds 5, HLL mean and contact speed 66, star state 25,
+# flux 24, psi flux 1 -> 263 against 148 for Rusanov: 115 more per face.
+HLLC_EXTRA_PER_FACE = 115
 
 # MI355X vector peak for FP32 (non-packed) and FP64: 256 CUs x 4 SIMDs x
 # 16 lanes x 2 (FMA) x 2.4 GHz = 78.6 TFLOP/s
@@ -235,7 +243,7 @@ def time_regrid(sim, wl):
     return out
 
 
-def time_weno(wl, precision, steps, autotune=True):
+def time_weno(wl, precision, steps, autotune=True, riemann="rusanov"):
     """Whole WENO cycles (two stages, the boundary procedure on the stage,
     reflux, restriction, fill) on the same blocks and initial data, captured
     in a HIP graph, and map_step alone (both stages with the stage's
@@ -244,7 +252,7 @@ def time_weno(wl, precision, steps, autotune=True):
     import torch
     from paper_1204_5849_amd import native as N
     from paper_1204_5849_amd.sim import Simulation
-    ww = dataclasses.replace(wl, scheme="weno")
+    ww = dataclasses.replace(wl, scheme="weno", riemann=riemann)
     sim = Simulation(ww, precision=precision)
     sim.load_initial()
     if autotune:
@@ -271,7 +279,9 @@ def time_weno(wl, precision, steps, autotune=True):
     t_step = e0.elapsed_time(e1) / 5 * 1e-3
     cells = ww.n_leaf_cells()
     f1, f2 = WENO_FLOPS_PER_CELL[(ww.ndim, ww.eta > 0)]
-    out_d = {"ms_per_step": el / steps * 1e3, "value": cells * steps / el, "unit": "cell-updates/s",
+    if riemann == "hllc":
+        f1, f2 = f1 + ww.ndim * HLLC_EXTRA_PER_FACE, f2 + ww.ndim * HLLC_EXTRA_PER_FACE
+    out_d = {"riemann": riemann, "ms_per_step": el / steps * 1e3, "value": cells * steps / el, "unit": "cell-updates/s",
              "steps": steps, "step_ms": t_step * 1e3, "flags": [int(c) for c in cnt],
              "flops_per_cell_update_stages": [f1, f2],
              "note": "stage kernels k_step3/k_step2 <..., 1|2, 0>; per-stage durations in the "
@@ -406,6 +416,12 @@ def main():
         result["weno"] = time_weno(wl, args.precision, args.weno_steps, not args.no_autotune)
         r = result["weno"]
         log(f"weno: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.3f} G cell-updates/s, "
+            f"map_step {r['step_ms']:.3f} ms")
+        log("WENO + TVD Runge-Kutta 2 with the HLLC flux on the same workload")
+        result["weno_hllc"] = time_weno(wl, args.precision, args.weno_steps, not args.no_autotune,
+                                        riemann="hllc")
+        r = result["weno_hllc"]
+        log(f"weno+hllc: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.3f} G cell-updates/s, "
             f"map_step {r['step_ms']:.3f} ms")
 
     if not args.no_plain:

@@ -52,6 +52,7 @@ enum { MAP_GLM_PAPER = 0, MAP_GLM_FASTSPEED = 1 };
 enum { MAP_BC_PERIODIC = 0, MAP_BC_OUTFLOW = 1 };
 enum { MAP_LAUNCH_BATCHED = 0, MAP_LAUNCH_PER_BLOCK = 1 };
 enum { MAP_EST_VAR = 0, MAP_EST_BMAG = 1 };
+enum { MAP_RUSANOV = 0, MAP_HLLC = 1 };
 
 /* Scheme parameters (Sec. 2 and 3).
  *   precision     MAP_FP64: state and arithmetic in FP64.  MAP_FP32_MIXED:
@@ -70,9 +71,14 @@ enum { MAP_EST_VAR = 0, MAP_EST_BMAG = 1 };
  *                 step; MAP_GLM_FASTSPEED: c_h = alpha_g, factor
  *                 exp(-dt c_h/glm_cr).
  *   eglm_sources  1: EGLM sources -(div B)B and -B.grad(psi); 0: plain GLM.
+ *   riemann       face flux of LF and WENO: MAP_RUSANOV (the Lax-Friedrichs
+ *                 flux printed in Sec. 3.2) or MAP_HLLC (the HLLC solver the
+ *                 paper names for MHD, Sec. 3.2 and 5.2; the GLM pair takes
+ *                 its exact upwind flux and the normal field its interface
+ *                 value).  MMC has no Riemann solver: MAP_HLLC is MAP_EINVAL.
  *   eta           uniform resistivity (0 = off), Sec. 3.5. */
 typedef struct {
-    int ndim, precision, scheme, limiter, glm_mode, eglm_sources;
+    int ndim, precision, scheme, limiter, glm_mode, eglm_sources, riemann;
     double gamma, cfl, glm_cd, glm_cr, eta;
 } map_params;
 

@@ -160,6 +160,7 @@ map_status run_step_kernel(map_ctx *c, int sch, const void *Uin, void *Uout, con
     a.eta = c->p.eta;
     a.eglm = c->p.eglm_sources;
     a.limiter = c->p.limiter;
+    a.riemann = c->p.riemann;
     const bool resist = c->p.eta > 0.0;
     auto launch = [&](const StepArgs &x, int grid) -> hipError_t {
         if (c->p.scheme == MAP_MMC)

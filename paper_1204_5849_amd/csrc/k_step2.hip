@@ -44,7 +44,7 @@ constexpr int NCOL2 = NB + 2;      // computing columns per block
 constexpr int NXT2 = 2 * BPW2;     // load-only cells (x = -2, x = 17) per row
 }  // namespace
 
-template <typename T, bool MIXED, bool RESIST, int SCH, int LIM>
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS>
 __global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
 {
     constexpr int XS = XS2, BPW = BPW2, P = P2, FC = NB;
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
                 // the flux of the face k-1/2 from registers only, formed
                 // before the barriers so that its states die early
                 if (inI && k >= 0)
-                    rusanov_p<1>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
+                    face_flux<RS, 1>(Lm_prev, pLm_prev, Rm, pRm, gam, ph.gm1, ch, ch2, fmc);
                 // EGLM sources from central differences of u^n
                 if (a.eglm && inI && kI) {
                     const T *bx = sc + (lb * NV + BX) * XS;
@@ -401,7 +401,7 @@ __global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     R[v] = srf[(lb * NV + v) * XS + q + 1];
-                rusanov_p<0>(Lin, pLin, R, spr[lb * XS + q + 1], gam, ch, ch2, fin);
+                face_flux<RS, 0>(Lin, pLin, R, spr[lb * XS + q + 1], gam, ph.gm1, ch, ch2, fin);
             }
             if constexpr (RESIST) {
                 if (inI && kI) {
@@ -503,29 +503,37 @@ __global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
     }
 }
 
-template <typename T, bool MIXED, bool RESIST, int SCH, int LIM>
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS>
 static hipError_t launch2(const StepArgs &a, int grid, hipStream_t s)
 {
     const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
-    hipLaunchKernelGGL((k_step2<T, MIXED, RESIST, SCH, LIM>), dim3(g), dim3(NT2), 0, s, a);
+    hipLaunchKernelGGL((k_step2<T, MIXED, RESIST, SCH, LIM, RS>), dim3(g), dim3(NT2), 0, s, a);
     return hipGetLastError();
 }
 
 // LF: one instance per limiter; WENO stages use no limiter
-template <typename T, bool MIXED, bool RESIST>
+template <typename T, bool MIXED, bool RESIST, int RS>
 static hipError_t launch2_sch(int sch, const StepArgs &a, int grid, hipStream_t s)
+{
+    if (sch == SCH_WENO1)
+        return launch2<T, MIXED, RESIST, SCH_WENO1, MAP_MINMOD, RS>(a, grid, s);
+    if (sch == SCH_WENO2)
+        return launch2<T, MIXED, RESIST, SCH_WENO2, MAP_MINMOD, RS>(a, grid, s);
+    if (a.limiter == MAP_MINMOD)
+        return launch2<T, MIXED, RESIST, SCH_LF, MAP_MINMOD, RS>(a, grid, s);
+    if (a.limiter == MAP_VANLEER)
+        return launch2<T, MIXED, RESIST, SCH_LF, MAP_VANLEER, RS>(a, grid, s);
+    return launch2<T, MIXED, RESIST, SCH_LF, MAP_PAPER_PHI, RS>(a, grid, s);
+}
+
+template <typename T, bool MIXED, bool RESIST>
+static hipError_t launch2_rs(int sch, const StepArgs &a, int grid, hipStream_t s)
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    if (sch == SCH_WENO1)
-        return launch2<T, MIXED, RESIST, SCH_WENO1, MAP_MINMOD>(a, grid, s);
-    if (sch == SCH_WENO2)
-        return launch2<T, MIXED, RESIST, SCH_WENO2, MAP_MINMOD>(a, grid, s);
-    if (a.limiter == MAP_MINMOD)
-        return launch2<T, MIXED, RESIST, SCH_LF, MAP_MINMOD>(a, grid, s);
-    if (a.limiter == MAP_VANLEER)
-        return launch2<T, MIXED, RESIST, SCH_LF, MAP_VANLEER>(a, grid, s);
-    return launch2<T, MIXED, RESIST, SCH_LF, MAP_PAPER_PHI>(a, grid, s);
+    if (a.riemann == MAP_HLLC)
+        return launch2_sch<T, MIXED, RESIST, MAP_HLLC>(sch, a, grid, s);
+    return launch2_sch<T, MIXED, RESIST, MAP_RUSANOV>(sch, a, grid, s);
 }
 
 int step_blocks_per_group(int ndim, int scheme)
@@ -538,10 +546,10 @@ int step_blocks_per_group(int ndim, int scheme)
 hipError_t launch_step2(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s)
 {
     if (fp64)
-        return resist ? launch2_sch<double, false, true>(sch, a, grid, s)
-                      : launch2_sch<double, false, false>(sch, a, grid, s);
-    return resist ? launch2_sch<float, true, true>(sch, a, grid, s)
-                  : launch2_sch<float, true, false>(sch, a, grid, s);
+        return resist ? launch2_rs<double, false, true>(sch, a, grid, s)
+                      : launch2_rs<double, false, false>(sch, a, grid, s);
+    return resist ? launch2_rs<float, true, true>(sch, a, grid, s)
+                  : launch2_rs<float, true, false>(sch, a, grid, s);
 }
 
 }  // namespace mapk

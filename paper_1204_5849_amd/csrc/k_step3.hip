@@ -53,7 +53,7 @@ constexpr int OPW = NOUT / 4;         // outer cells per wave (20)
 static_assert(NB == 16 && NT3 == 256, "lane layout assumes 16^3 blocks");
 }  // namespace
 
-template <typename T, bool MIXED, bool RESIST, int SCH, int LIM>
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS>
 __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs a)
 {
     constexpr int SY = PD;
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
                 // the flux of the face k-1/2 from registers only: formed here,
                 // before the barriers, so that its states die early
                 if (k >= 0)
-                    rusanov_p<2>(Lm_prev, pLm_prev, Rm, pRm, gam, ch, ch2, fmc);
+                    face_flux<RS, 2>(Lm_prev, pLm_prev, Rm, pRm, gam, ph.gm1, ch, ch2, fmc);
                 // EGLM sources from central differences of u^n
                 if (a.eglm && kI) {
                     const T *bx = sc + BX * XS3, *by = sc + BY * XS3, *ps = sc + PSI * XS3;
@@ -507,11 +507,11 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     R[v] = srf[(0 * NV + v) * XS3 + q + 1];
-                rusanov_p<0>(Lin[0], pLin[0], R, spr[q + 1], gam, ch, ch2, fin[0]);
+                face_flux<RS, 0>(Lin[0], pLin[0], R, spr[q + 1], gam, ph.gm1, ch, ch2, fin[0]);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     R[v] = srf[(1 * NV + v) * XS3 + q + SY];
-                rusanov_p<1>(Lin[1], pLin[1], R, spr[XS3 + q + SY], gam, ch, ch2, fin[1]);
+                face_flux<RS, 1>(Lin[1], pLin[1], R, spr[XS3 + q + SY], gam, ph.gm1, ch, ch2, fin[1]);
             }
             if (kI && isring && rlo) {
                 // the ring cell's own state is the left one; the flux replaces
@@ -525,9 +525,9 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
                 }
                 const T pl = spr[rdim * XS3 + xq], pr = spr[rdim * XS3 + qn];
                 if (rdim == 0)
-                    rusanov_p<0>(L, pl, R, pr, gam, ch, ch2, f);
+                    face_flux<RS, 0>(L, pl, R, pr, gam, ph.gm1, ch, ch2, f);
                 else
-                    rusanov_p<1>(L, pl, R, pr, gam, ch, ch2, f);
+                    face_flux<RS, 1>(L, pl, R, pr, gam, ph.gm1, ch, ch2, f);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     srf[(rdim * NV + v) * XS3 + xq] = f[v];
@@ -659,38 +659,46 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
     }
 }
 
-template <typename T, bool MIXED, bool RESIST, int SCH, int LIM>
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS>
 static hipError_t launch3(const StepArgs &a, int grid, hipStream_t s)
 {
     const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
-    hipLaunchKernelGGL((k_step3<T, MIXED, RESIST, SCH, LIM>), dim3(g), dim3(NT3), 0, s, a);
+    hipLaunchKernelGGL((k_step3<T, MIXED, RESIST, SCH, LIM, RS>), dim3(g), dim3(NT3), 0, s, a);
     return hipGetLastError();
 }
 
 // LF: one instance per limiter; WENO stages use no limiter
-template <typename T, bool MIXED, bool RESIST>
+template <typename T, bool MIXED, bool RESIST, int RS>
 static hipError_t launch3_sch(int sch, const StepArgs &a, int grid, hipStream_t s)
+{
+    if (sch == SCH_WENO1)
+        return launch3<T, MIXED, RESIST, SCH_WENO1, MAP_MINMOD, RS>(a, grid, s);
+    if (sch == SCH_WENO2)
+        return launch3<T, MIXED, RESIST, SCH_WENO2, MAP_MINMOD, RS>(a, grid, s);
+    if (a.limiter == MAP_MINMOD)
+        return launch3<T, MIXED, RESIST, SCH_LF, MAP_MINMOD, RS>(a, grid, s);
+    if (a.limiter == MAP_VANLEER)
+        return launch3<T, MIXED, RESIST, SCH_LF, MAP_VANLEER, RS>(a, grid, s);
+    return launch3<T, MIXED, RESIST, SCH_LF, MAP_PAPER_PHI, RS>(a, grid, s);
+}
+
+template <typename T, bool MIXED, bool RESIST>
+static hipError_t launch3_rs(int sch, const StepArgs &a, int grid, hipStream_t s)
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    if (sch == SCH_WENO1)
-        return launch3<T, MIXED, RESIST, SCH_WENO1, MAP_MINMOD>(a, grid, s);
-    if (sch == SCH_WENO2)
-        return launch3<T, MIXED, RESIST, SCH_WENO2, MAP_MINMOD>(a, grid, s);
-    if (a.limiter == MAP_MINMOD)
-        return launch3<T, MIXED, RESIST, SCH_LF, MAP_MINMOD>(a, grid, s);
-    if (a.limiter == MAP_VANLEER)
-        return launch3<T, MIXED, RESIST, SCH_LF, MAP_VANLEER>(a, grid, s);
-    return launch3<T, MIXED, RESIST, SCH_LF, MAP_PAPER_PHI>(a, grid, s);
+    if (a.riemann == MAP_HLLC)
+        return launch3_sch<T, MIXED, RESIST, MAP_HLLC>(sch, a, grid, s);
+    return launch3_sch<T, MIXED, RESIST, MAP_RUSANOV>(sch, a, grid, s);
 }
 
 hipError_t launch_step3(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s)
 {
     if (fp64)
-        return resist ? launch3_sch<double, false, true>(sch, a, grid, s)
-                      : launch3_sch<double, false, false>(sch, a, grid, s);
-    return resist ? launch3_sch<float, true, true>(sch, a, grid, s)
-                  : launch3_sch<float, true, false>(sch, a, grid, s);
+        return resist ? launch3_rs<double, false, true>(sch, a, grid, s)
+                      : launch3_rs<double, false, false>(sch, a, grid, s);
+    return resist ? launch3_rs<float, true, true>(sch, a, grid, s)
+                  : launch3_rs<float, true, false>(sch, a, grid, s);
 }
 
 }  // namespace mapk

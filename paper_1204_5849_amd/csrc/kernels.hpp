@@ -28,7 +28,7 @@ struct StepArgs {
     void *fbuf;
     unsigned long long *cnt;
     double gamma, eta;
-    int eglm, limiter;
+    int eglm, limiter, riemann;
 };
 
 struct FillArgs {

@@ -202,9 +202,9 @@ __device__ __forceinline__ void flux_w(const T u[NV], const Prim<T> &w, T ch2, T
     flux_sel(u, w, D, ch2, f);
 }
 
-// |v_d| + c_f,d from a state and its primitives (d as in flux_sel)
+// fast magnetosonic speed c_f,d from a state and its primitives
 template <typename T>
-__device__ __forceinline__ T speed_sel(const T u[NV], const Prim<T> &w, int d, T gamma)
+__device__ __forceinline__ T fast_sel(const T u[NV], const Prim<T> &w, int d, T gamma)
 {
     const T a2 = gamma * w.p * w.ir;
     const T b2 = w.bb * w.ir;
@@ -214,8 +214,15 @@ __device__ __forceinline__ T speed_sel(const T u[NV], const Prim<T> &w, int d, T
     disc = disc < T(0) ? T(0) : disc;
     T cf2 = T(0.5) * (s + Num<T>::sqrt_(disc));
     cf2 = cf2 < T(0) ? T(0) : cf2;
+    return Num<T>::sqrt_(cf2);
+}
+
+// |v_d| + c_f,d from a state and its primitives (d as in flux_sel)
+template <typename T>
+__device__ __forceinline__ T speed_sel(const T u[NV], const Prim<T> &w, int d, T gamma)
+{
     const T vd = d == 0 ? w.vx : (d == 1 ? w.vy : w.vz);
-    return fabs(vd) + Num<T>::sqrt_(cf2);
+    return fabs(vd) + fast_sel(u, w, d, gamma);
 }
 
 template <int D, typename T>

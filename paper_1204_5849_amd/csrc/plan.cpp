@@ -83,6 +83,14 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
         err = "the MMC scheme is built for 2-D blocks only";
         return MAP_EINVAL;
     }
+    if (p->riemann != MAP_RUSANOV && p->riemann != MAP_HLLC) {
+        err = "unknown riemann solver";
+        return MAP_EINVAL;
+    }
+    if (p->scheme == MAP_MMC && p->riemann != MAP_RUSANOV) {
+        err = "MMC uses Lax-Friedrichs splitting, not a Riemann solver";
+        return MAP_EINVAL;
+    }
     if (nsims >= (1 << 15)) {
         err = "too many simulations";
         return MAP_EINVAL;

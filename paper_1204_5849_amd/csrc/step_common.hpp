@@ -65,11 +65,120 @@ __device__ __forceinline__ void rusanov_sel(const T L[NV], T pL, const T R[NV], 
     }
 }
 
-template <int D, typename T>
-__device__ __forceinline__ void rusanov_p(const T L[NV], T pL, const T R[NV], T pR, T gamma,
+// HLLC flux (the solver the paper names for MHD, Gurski's construction with
+// the intermediate states of Li's HLLC for MHD) across a face normal to d.
+// The GLM pair (B_d, psi) takes the exact upwind flux of its linear system:
+// interface values B_m = (B_dL + B_dR)/2 - (psi_R - psi_L)/(2 c_h) and
+// psi_m = (psi_L + psi_R)/2 - c_h (B_dR - B_dL)/2, fluxes psi_m and
+// c_h^2 B_m.  Both states then take B_d = B_m (their gas pressures follow,
+// e unchanged), and the other components get the HLLC fan: outer speeds
+// S_L = min(v_L, v_R) - max(c_fL, c_fR), S_R = max(v_L, v_R) + max(c_fL, c_fR);
+// the HLL mean state; contact speed S_M = (rho v_d)_hll / rho_hll; star
+// total pressure p* = rho_K (S_K - v_K)(S_M - v_K) + p_T,K (mean of both
+// sides); on the side K of the face's region
+//   rho* = rho_K (S_K - v_K)/(S_K - S_M), (rho v_d)* = rho* S_M,
+//   (rho v_t)* = [rho_K v_t,K (S_K - v_K) - B_m (B_t,hll - B_t,K)]/(S_K - S_M),
+//   B_t* = B_t,hll,
+//   e* = [e_K (S_K - v_K) - p_T,K v_K + p* S_M + B_m (v_K.B_K - v_hll.B_hll)]/(S_K - S_M),
+// and the flux F_K + S_K (U*_K - U_K), or F_L / F_R when the whole fan
+// moves one way.
+template <typename T>
+__device__ __forceinline__ void hllc_sel(const T L0[NV], T pL0, const T R0[NV], T pR0, int d,
+                                         T gamma, T gm1, T ch, T ch2, T f[NV])
+{
+    const T h = T(0.5);
+    const int kB = BX + d;
+    const T BdL = L0[kB], BdR = R0[kB];
+    T Bm, psim;
+    if (ch > T(0)) {
+        Bm = h * (BdL + BdR) - Num<T>::div(R0[PSI] - L0[PSI], T(2) * ch);
+        psim = h * (L0[PSI] + R0[PSI]) - h * ch * (BdR - BdL);
+    } else {
+        Bm = h * (BdL + BdR);
+        psim = h * (L0[PSI] + R0[PSI]);
+    }
+    T U[2][NV], F[2][NV], v[2], pt[2], cf[2], vb[2];
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        const T *u0 = s ? R0 : L0;
+        const T Bd0 = s ? BdR : BdL;
+#pragma unroll
+        for (int k = 0; k < NV; k++)
+            U[s][k] = k == kB ? Bm : u0[k];
+        Prim<T> w;
+        w.ir = Num<T>::rcp(U[s][RHO]);
+        w.vx = U[s][MX] * w.ir;
+        w.vy = U[s][MY] * w.ir;
+        w.vz = U[s][MZ] * w.ir;
+        w.bb = U[s][BX] * U[s][BX] + U[s][BY] * U[s][BY] + U[s][BZ] * U[s][BZ];
+        w.p = (s ? pR0 : pL0) + gm1 * (h * ((Bd0 - Bm) * (Bd0 + Bm)));
+        flux_sel(U[s], w, d, ch2, F[s]);
+        v[s] = d == 0 ? w.vx : (d == 1 ? w.vy : w.vz);
+        pt[s] = w.p + h * w.bb;
+        cf[s] = fast_sel(U[s], w, d, gamma);
+        vb[s] = w.vx * U[s][BX] + w.vy * U[s][BY] + w.vz * U[s][BZ];
+    }
+    const T cmax = cf[0] > cf[1] ? cf[0] : cf[1];
+    const T SL = (v[0] < v[1] ? v[0] : v[1]) - cmax;
+    const T SR = (v[0] > v[1] ? v[0] : v[1]) + cmax;
+    if (SL >= T(0) || SR <= T(0)) {
+        const bool left = SL >= T(0);
+#pragma unroll
+        for (int k = 0; k < NV; k++)
+            f[k] = left ? F[0][k] : F[1][k];
+    } else {
+        const T r = Num<T>::rcp(SR - SL);
+        T hl[NV];
+#pragma unroll
+        for (int k = 0; k < EN; k++)
+            hl[k] = (SR * U[1][k] - SL * U[0][k] - F[1][k] + F[0][k]) * r;
+        hl[kB] = Bm;
+        const T irh = Num<T>::rcp(hl[RHO]);
+        const T vh[3] = {hl[MX] * irh, hl[MY] * irh, hl[MZ] * irh};
+        const T SM = d == 0 ? vh[0] : (d == 1 ? vh[1] : vh[2]);
+        const T vbh = vh[0] * hl[BX] + vh[1] * hl[BY] + vh[2] * hl[BZ];
+        const T ps0 = U[0][RHO] * (SL - v[0]) * (SM - v[0]) + pt[0];
+        const T ps1 = U[1][RHO] * (SR - v[1]) * (SM - v[1]) + pt[1];
+        const T pst = h * (ps0 + ps1);
+        const bool right = SM < T(0);
+        const T S = right ? SR : SL;
+        const T vs = right ? v[1] : v[0];
+        const T pts = right ? pt[1] : pt[0];
+        const T vbs = right ? vb[1] : vb[0];
+        T us[NV], fs[NV];
+#pragma unroll
+        for (int k = 0; k < NV; k++) {
+            us[k] = right ? U[1][k] : U[0][k];
+            fs[k] = right ? F[1][k] : F[0][k];
+        }
+        const T sv = S - vs;
+        const T iden = Num<T>::rcp(S - SM);
+        T st[NV];
+        st[RHO] = us[RHO] * sv * iden;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            st[MX + j] = j == d ? st[RHO] * SM
+                                : (us[MX + j] * sv - Bm * (hl[BX + j] - us[BX + j])) * iden;
+            st[BX + j] = j == d ? Bm : hl[BX + j];
+        }
+        st[EN] = (us[EN] * sv - pts * vs + pst * SM + Bm * (vbs - vbh)) * iden;
+#pragma unroll
+        for (int k = 0; k < EN + 1; k++)
+            f[k] = fs[k] + S * (st[k] - us[k]);
+    }
+    f[kB] = psim;
+    f[PSI] = ch2 * Bm;
+}
+
+// the face flux of the scheme's Riemann solver (RS = MAP_RUSANOV or MAP_HLLC)
+template <int RS, int D, typename T>
+__device__ __forceinline__ void face_flux(const T L[NV], T pL, const T R[NV], T pR, T gamma, T gm1,
                                           T ch, T ch2, T f[NV])
 {
-    rusanov_sel(L, pL, R, pR, D, gamma, ch, ch2, f);
+    if constexpr (RS == MAP_HLLC)
+        hllc_sel(L, pL, R, pR, D, gamma, gm1, ch, ch2, f);
+    else
+        rusanov_sel(L, pL, R, pR, D, gamma, ch, ch2, f);
 }
 
 }  // namespace mapk

@@ -20,12 +20,14 @@ MAP_GLM_PAPER, MAP_GLM_FASTSPEED = 0, 1
 MAP_BC_PERIODIC, MAP_BC_OUTFLOW = 0, 1
 MAP_LAUNCH_BATCHED, MAP_LAUNCH_PER_BLOCK = 0, 1
 MAP_EST_VAR, MAP_EST_BMAG = 0, 1
+MAP_RUSANOV, MAP_HLLC = 0, 1
 
 SCHEMES = {"lf": MAP_LF, "mmc": MAP_MMC, "weno": MAP_WENO}
 LIMITERS = {"minmod": MAP_MINMOD, "vanleer": MAP_VANLEER, "paper": MAP_PAPER_PHI}
 GLM = {"paper": MAP_GLM_PAPER, "fastspeed": MAP_GLM_FASTSPEED}
 BC = {"periodic": MAP_BC_PERIODIC, "outflow": MAP_BC_OUTFLOW}
 PRECISION = {"fp64": MAP_FP64, "fp32": MAP_FP32_MIXED}
+RIEMANN = {"rusanov": MAP_RUSANOV, "hllc": MAP_HLLC}
 
 EXPORTS = ["map_init_blocks", "map_query", "map_neighbors", "map_bind_workspace",
            "map_prim_to_cons", "map_fill_ghosts", "map_restrict", "map_prolong", "map_cfl_dt",
@@ -43,7 +45,8 @@ class MapError(RuntimeError):
 class map_params(C.Structure):
     _fields_ = [("ndim", C.c_int), ("precision", C.c_int), ("scheme", C.c_int),
                 ("limiter", C.c_int), ("glm_mode", C.c_int), ("eglm_sources", C.c_int),
-                ("gamma", C.c_double), ("cfl", C.c_double), ("glm_cd", C.c_double),
+                ("riemann", C.c_int), ("gamma", C.c_double), ("cfl", C.c_double),
+                ("glm_cd", C.c_double),
                 ("glm_cr", C.c_double), ("eta", C.c_double)]
 
 
@@ -142,7 +145,8 @@ def _p(x):
 
 # ---------------------------------------------------------------- thin wrappers
 def make_params(ndim, precision="fp64", scheme="lf", limiter="minmod", glm_mode="paper",
-                eglm_sources=True, gamma=5.0 / 3.0, cfl=0.4, cd=0.18, cr=0.18, eta=0.0):
+                eglm_sources=True, gamma=5.0 / 3.0, cfl=0.4, cd=0.18, cr=0.18, eta=0.0,
+                riemann="rusanov"):
     p = map_params()
     p.ndim = ndim
     p.precision = PRECISION.get(precision, precision)
@@ -150,6 +154,7 @@ def make_params(ndim, precision="fp64", scheme="lf", limiter="minmod", glm_mode=
     p.limiter = LIMITERS.get(limiter, limiter)
     p.glm_mode = GLM.get(glm_mode, glm_mode)
     p.eglm_sources = int(bool(eglm_sources))
+    p.riemann = RIEMANN.get(riemann, riemann)
     p.gamma, p.cfl, p.glm_cd, p.glm_cr, p.eta = gamma, cfl, cd, cr, eta
     return p
 

@@ -27,7 +27,7 @@ class Simulation:
         self.precision = precision or wl.precision
         self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
         self.params = N.make_params(wl.ndim, precision=self.precision, scheme=wl.scheme,
-                                    limiter=wl.limiter, glm_mode=wl.glm_mode,
+                                    limiter=wl.limiter, glm_mode=wl.glm_mode, riemann=wl.riemann,
                                     eglm_sources=wl.eglm_sources, gamma=wl.gamma, cfl=wl.cfl,
                                     cd=wl.cd, cr=wl.cr, eta=wl.eta)
         self.ctx = N.map_init_blocks(self.params, wl.sims, wl.keys)

@@ -75,6 +75,10 @@ def test_param_errors():
     assert _status(N.make_params(4), sims, base) == N.MAP_EINVAL
     assert _status(N.make_params(2, limiter=7), sims, base) == N.MAP_EINVAL
     assert _status(N.make_params(2, gamma=1.0), sims, base) == N.MAP_EINVAL
+    assert _status(N.make_params(2, riemann=5), sims, base) == N.MAP_EINVAL
+    # MMC splits fluxes (Sec. 3.1); it has no Riemann solver to replace
+    assert _status(N.make_params(2, scheme="mmc", riemann="hllc"), sims, base) == N.MAP_EINVAL
+    assert _status(N.make_params(2, scheme="weno", riemann="hllc"), sims, base) == N.MAP_OK
     sims3 = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=(2, 2, 2), bc=(("periodic",) * 2,) * 3)]
     assert _status(N.make_params(3, scheme="mmc"), sims3, W.base_keys(0, (2, 2, 2), 3)) == N.MAP_EINVAL
     mixed = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=(2, 2, 1),
