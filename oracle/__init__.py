@@ -29,12 +29,14 @@ MINMOD, VANLEER, PAPER_PHI = 0, 1, 2
 GLM_PAPER, GLM_FASTSPEED = 0, 1
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 RUSANOV, HLLC = 0, 1
+COND_OFF, COND_ISO, COND_FIELD = 0, 1, 2
 
 _SCHEMES = {"lf": LF, "mmc": MMC, "weno": WENO}
 _LIMITERS = {"minmod": MINMOD, "vanleer": VANLEER, "paper": PAPER_PHI}
 _GLM = {"paper": GLM_PAPER, "fastspeed": GLM_FASTSPEED}
 _BC = {"periodic": BC_PERIODIC, "outflow": BC_OUTFLOW}
 _RIEMANN = {"rusanov": RUSANOV, "hllc": HLLC}
+_COND = {"off": COND_OFF, "iso": COND_ISO, "field": COND_FIELD}
 
 
 def build(force: bool = True) -> str:
@@ -52,13 +54,16 @@ def build(force: bool = True) -> str:
 class Params(C.Structure):
     _fields_ = [("ndim", C.c_int), ("physics", C.c_int), ("scheme", C.c_int),
                 ("limiter", C.c_int), ("glm_mode", C.c_int), ("eglm_sources", C.c_int),
-                ("riemann", C.c_int), ("gamma", C.c_double), ("cfl", C.c_double), ("cd", C.c_double),
-                ("cr", C.c_double), ("eta", C.c_double), ("adv", C.c_double * 3)]
+                ("riemann", C.c_int), ("cond_mode", C.c_int), ("cond_max_sub", C.c_int),
+                ("gamma", C.c_double), ("cfl", C.c_double), ("cd", C.c_double),
+                ("cr", C.c_double), ("eta", C.c_double), ("kappa0", C.c_double),
+                ("kappa_exp", C.c_double), ("adv", C.c_double * 3)]
 
 
 class DtRec(C.Structure):
     _fields_ = [("dt", C.c_double), ("ch", C.c_double), ("damp", C.c_double),
-                ("alpha", C.c_double)]
+                ("alpha", C.c_double), ("dt_sub", C.c_double), ("nsub", C.c_int),
+                ("reserved", C.c_int)]
 
     def as_tuple(self):
         return (self.dt, self.ch, self.damp, self.alpha)
@@ -105,7 +110,11 @@ def lib():
         L.orc_resistive.argtypes = [pp, dp, dp, ip, dp]
         L.orc_tile_maxspeed.argtypes = [pp, dp, ip]
         L.orc_tile_maxspeed.restype = C.c_double
-        L.orc_make_dtrec.argtypes = [pp, C.c_double, C.c_double, C.POINTER(DtRec)]
+        L.orc_make_dtrec.argtypes = [pp, C.c_double, C.c_double, C.c_double, C.POINTER(DtRec)]
+        L.orc_tile_cond_rate.argtypes = [pp, dp, ip]
+        L.orc_tile_cond_rate.restype = C.c_double
+        L.orc_conduct_tile.argtypes = [pp, dp, dp, ip, C.c_double, dp, dp]
+        L.orc_amr_conduct.argtypes = [C.c_void_p, C.POINTER(DtRec)]
         L.orc_grid_fill.argtypes = [pp, dp, ip, ip]
         L.orc_grid_run.argtypes = [pp, dp, dp, ip, ip, C.c_int, dp, lp]
         L.orc_amr_new.argtypes = [pp, C.c_int, C.c_int, C.POINTER(Sim), C.c_int, C.POINTER(Key)]
@@ -143,7 +152,8 @@ def _ip(a):
 
 def make_params(ndim=2, physics=MHD, scheme="lf", limiter="minmod", glm_mode="paper",
                 eglm_sources=True, gamma=5.0 / 3.0, cfl=0.4, cd=0.18, cr=0.18, eta=0.0,
-                adv=(0.0, 0.0, 0.0), riemann="rusanov") -> Params:
+                adv=(0.0, 0.0, 0.0), riemann="rusanov", cond="off", cond_max_sub=8,
+                kappa0=0.0, kappa_exp=2.5) -> Params:
     p = Params()
     p.ndim = ndim
     p.physics = physics
@@ -152,6 +162,9 @@ def make_params(ndim=2, physics=MHD, scheme="lf", limiter="minmod", glm_mode="pa
     p.glm_mode = _GLM.get(glm_mode, glm_mode)
     p.eglm_sources = int(bool(eglm_sources))
     p.riemann = _RIEMANN.get(riemann, riemann)
+    p.cond_mode = _COND.get(cond, cond)
+    p.cond_max_sub = cond_max_sub
+    p.kappa0, p.kappa_exp = kappa0, kappa_exp
     p.gamma, p.cfl, p.cd, p.cr, p.eta = gamma, cfl, cd, cr, eta
     for i in range(3):
         p.adv[i] = adv[i]
@@ -161,7 +174,8 @@ def make_params(ndim=2, physics=MHD, scheme="lf", limiter="minmod", glm_mode="pa
 def params_from_workload(w) -> Params:
     return make_params(ndim=w.ndim, scheme=w.scheme, limiter=w.limiter, glm_mode=w.glm_mode,
                        eglm_sources=w.eglm_sources, gamma=w.gamma, cfl=w.cfl, cd=w.cd,
-                       cr=w.cr, eta=w.eta, riemann=w.riemann)
+                       cr=w.cr, eta=w.eta, riemann=w.riemann, cond=w.cond,
+                       cond_max_sub=w.cond_max_sub, kappa0=w.kappa0, kappa_exp=w.kappa_exp)
 
 
 def nvar(p: Params) -> int:
@@ -222,9 +236,9 @@ def prim_to_cons(p, w):
     return w
 
 
-def dtrec(p, alpha, dxmin) -> DtRec:
+def dtrec(p, alpha, dxmin, kmax=0.0) -> DtRec:
     r = DtRec()
-    lib().orc_make_dtrec(C.byref(p), alpha, dxmin, C.byref(r))
+    lib().orc_make_dtrec(C.byref(p), alpha, dxmin, kmax, C.byref(r))
     return r
 
 
@@ -302,6 +316,33 @@ def tile_maxspeed(p, u, n):
     n3c, n3p = _ip(_n3(p, n))
     u = np.ascontiguousarray(u, dtype=np.float64)
     return lib().orc_tile_maxspeed(C.byref(p), _dp(u), n3p)
+
+
+def tile_cond_rate(p, u, n):
+    """Largest kappa T / p over the interior of a padded tile."""
+    n3c, n3p = _ip(_n3(p, n))
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return lib().orc_tile_cond_rate(C.byref(p), _dp(u), n3p)
+
+
+def conduct_tile(p, dx, u, n, dt_sub, want_faces=False):
+    """One conduction sub-step on a padded tile: (new interior energy
+    [nz, ny, nx], face fluxes or None)."""
+    n3 = _n3(p, n)
+    n3c, n3p = _ip(n3)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    dxa = np.ascontiguousarray(list(dx) + [1.0] * (3 - len(dx)), dtype=np.float64)[:3]
+    enew = np.zeros((n3[2], n3[1], n3[0]))
+    ff = None
+    if want_faces:
+        nf = 0
+        for d in range(p.ndim):
+            t1, t2 = (1 if d == 0 else 0), (1 if d == 2 else 2)
+            nf += 2 * nvar(p) * int(n3[t1]) * int(n3[t2])
+        ff = np.zeros(nf)
+    lib().orc_conduct_tile(C.byref(p), _dp(dxa), _dp(u), n3p, float(dt_sub), _dp(enew),
+                           _dp(ff) if ff is not None else None)
+    return enew, ff
 
 
 def _bc_arr(bc):

@@ -861,8 +861,11 @@ double orc_tile_maxspeed(const orc_params *p, const double *u, const int n_in[3]
 }
 
 /* dt = c_cfl min(dx)/(n_dim alpha_g) (Sec. 3.7); resistive limit by analogy
- * with the conduction step of Sec. 3.4; c_h and the psi factor per GLM mode (Sec. 2). */
-void orc_make_dtrec(const orc_params *p, double alpha, double dxmin, orc_dtrec *o)
+ * with the conduction step of Sec. 3.4; c_h and the psi factor per GLM mode (Sec. 2).
+ * Conduction (Sec. 3.4): the sub-step limit dt_c = c_cfl min(dx)^2 /
+ * (n_dim max(kappa T/p)) with kmax = max(kappa T/p); the step is capped at
+ * cond_max_sub dt_c, and split into nsub = ceil(dt/dt_c) equal sub-steps. */
+void orc_make_dtrec(const orc_params *p, double alpha, double dxmin, double kmax, orc_dtrec *o)
 {
     int nd = p->ndim;
     double dt = p->cfl * dxmin / (nd * alpha);
@@ -870,6 +873,19 @@ void orc_make_dtrec(const orc_params *p, double alpha, double dxmin, orc_dtrec *
         double dr = p->cfl * dxmin * dxmin / (nd * p->eta);
         if (dr < dt)
             dt = dr;
+    }
+    o->dt_sub = 0.0;
+    o->nsub = 0;
+    o->reserved = 0;
+    if (p->physics == ORC_MHD && p->cond_mode != ORC_COND_OFF && kmax > 0.0) {
+        double dtc = p->cfl * dxmin * dxmin / (nd * kmax);
+        double cap = p->cond_max_sub * dtc;
+        if (cap < dt)
+            dt = cap;
+        double ns = ceil(dt / dtc);
+        int nsub = ns < 1.0 ? 1 : (ns > p->cond_max_sub ? p->cond_max_sub : (int)ns);
+        o->nsub = nsub;
+        o->dt_sub = dt / nsub;
     }
     o->dt = dt;
     o->alpha = alpha;
@@ -880,6 +896,148 @@ void orc_make_dtrec(const orc_params *p, double alpha, double dxmin, orc_dtrec *
         o->ch = alpha;
         o->damp = exp(-dt * o->ch / p->cr);
     }
+}
+
+/* ------------------------------------------------------------------ */
+/* thermal conduction sub-step (Sec. 3.4)                              */
+/* ------------------------------------------------------------------ */
+/* temperature T = p / rho (code units) */
+static double temperature(const orc_params *p, const double *u, long P, long c)
+{
+    double uc[NVMAX];
+    load(u, P, 9, c, uc);
+    return orc_pressure(p, uc) / uc[RHO];
+}
+
+/* kappa = kappa0 T^n for n a multiple of 1/2: whole powers by repeated
+ * multiplication, then one square root for the half */
+static double kappa_of(const orc_params *p, double T)
+{
+    int k = (int)lround(2.0 * p->kappa_exp);
+    double q = 1.0;
+    for (int i = 0; i < k / 2; i++)
+        q = q * T;
+    if (k & 1)
+        q = q * sqrt(T);
+    return p->kappa0 * q;
+}
+
+double orc_tile_cond_rate(const orc_params *p, const double *u, const int n_in[3])
+{
+    if (p->physics != ORC_MHD || p->cond_mode == ORC_COND_OFF)
+        return 0.0;
+    geo G = mkgeo(p->ndim, n_in);
+    double m = 0.0;
+    for (int z = 0; z < G.n[2]; z++)
+        for (int y = 0; y < G.n[1]; y++)
+            for (int x = 0; x < G.n[0]; x++) {
+                long c = at(&G, x, y, z);
+                double T = temperature(p, u, G.P, c);
+                /* kappa T / p = kappa / rho */
+                double r = kappa_of(p, T) / u[RHO * G.P + c];
+                if (r > m)
+                    m = r;
+            }
+    return m;
+}
+
+/* energy flux along +d across the face between the cells c and cn = c + s_d,
+ * F = -(kappa grad T)_d, in the conservative form de/dt + div F = 0 that the
+ * reflux of Sec. 4.3 corrects.
+ * Isotropic (the scheme of Sec. 3.4): -sqrt(kappa_c kappa_cn)(T_cn - T_c)/dx_d.
+ * Along the field (the form of the conduction test, Sec. 5): the same face
+ * kappa times b_d (b . grad T) with b = B_f/|B_f|, B_f the mean of the two
+ * cells' fields; grad T at the face: the difference across it along d and,
+ * along each other dimension e, the mean of the two cells' central
+ * differences; zero where B_f = 0. */
+static double cond_face(const orc_params *p, const geo *G, const double *Tc, const double *Kc,
+                        const double *u, long c, int d, const double dx[3])
+{
+    long cn = c + G->s[d];
+    double kf = sqrt(Kc[c] * Kc[cn]);
+    double gd = (Tc[cn] - Tc[c]) / dx[d];
+    if (p->cond_mode == ORC_COND_ISO)
+        return -(kf * gd);
+    double Bf[3], bb = 0.0;
+    for (int j = 0; j < 3; j++) {
+        Bf[j] = 0.5 * (u[(BX + j) * G->P + c] + u[(BX + j) * G->P + cn]);
+        bb += Bf[j] * Bf[j];
+    }
+    if (!(bb > 0.0))
+        return 0.0;
+    double bg = 0.0;
+    for (int e = 0; e < 3; e++) {
+        double g;
+        if (e == d) {
+            g = gd;
+        } else if (e < G->nd) {
+            long s = G->s[e];
+            g = ((Tc[c + s] - Tc[c - s]) + (Tc[cn + s] - Tc[cn - s])) / (4.0 * dx[e]);
+        } else {
+            g = 0.0;
+        }
+        bg += Bf[e] * g;
+    }
+    return -(kf * Bf[d] * bg / bb);
+}
+
+void orc_conduct_tile(const orc_params *p, const double dx[3], const double *u,
+                      const int n_in[3], double dt_sub, double *enew, double *ff)
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int nd = G.nd, nv = orc_nvar(p);
+    double *Tc = calloc(G.P, sizeof(double)), *Kc = calloc(G.P, sizeof(double));
+    /* T and kappa on the interior and the first ghost ring (edges and
+     * corners included) */
+    int lo[3], hi[3];
+    for (int d = 0; d < 3; d++) {
+        lo[d] = d < nd ? -1 : 0;
+        hi[d] = d < nd ? G.n[d] + 1 : 1;
+    }
+    for (int z = lo[2]; z < hi[2]; z++)
+        for (int y = lo[1]; y < hi[1]; y++)
+            for (int x = lo[0]; x < hi[0]; x++) {
+                long c = at(&G, x, y, z);
+                Tc[c] = temperature(p, u, G.P, c);
+                Kc[c] = kappa_of(p, Tc[c]);
+            }
+    for (int z = 0; z < G.n[2]; z++)
+        for (int y = 0; y < G.n[1]; y++)
+            for (int x = 0; x < G.n[0]; x++) {
+                long c = at(&G, x, y, z);
+                double acc = 0.0;
+                for (int d = 0; d < nd; d++) {
+                    double fp = cond_face(p, &G, Tc, Kc, u, c, d, dx);
+                    double fm = cond_face(p, &G, Tc, Kc, u, c - G.s[d], d, dx);
+                    acc += (fp - fm) / dx[d];
+                }
+                enew[interior_index(&G, x, y, z)] = u[EN * G.P + c] - dt_sub * acc;
+            }
+    if (ff) {
+        long off = 0;
+        for (int d = 0; d < nd; d++) {
+            int t1 = (d == 0) ? 1 : 0, t2 = (d == 2) ? 1 : 2;
+            long T = (long)G.n[t1] * G.n[t2];
+            for (int side = 0; side < 2; side++) {
+                int cd = side ? G.n[d] - 1 : -1;
+                for (int k = 0; k < nv; k++)
+                    for (int b = 0; b < G.n[t2]; b++)
+                        for (int a = 0; a < G.n[t1]; a++) {
+                            int xyz[3];
+                            xyz[d] = cd;
+                            xyz[t1] = a;
+                            xyz[t2] = b;
+                            double q = 0.0;
+                            if (k == EN)
+                                q = cond_face(p, &G, Tc, Kc, u, at(&G, xyz[0], xyz[1], xyz[2]), d, dx);
+                            ff[off + k * T + (long)b * G.n[t1] + a] = q;
+                        }
+                off += (long)nv * T;
+            }
+        }
+    }
+    free(Tc);
+    free(Kc);
 }
 
 /* ------------------------------------------------------------------ */
@@ -935,7 +1093,7 @@ void orc_grid_run(const orc_params *p, const double dx[3], double *u, const int 
     for (int it = 0; it < nsteps; it++) {
         orc_grid_fill(p, u, n_in, bc);
         orc_dtrec r;
-        orc_make_dtrec(p, orc_tile_maxspeed(p, u, n_in), dxmin, &r);
+        orc_make_dtrec(p, orc_tile_maxspeed(p, u, n_in), dxmin, orc_tile_cond_rate(p, u, n_in), &r);
         if (dt_trace)
             dt_trace[it] = r.dt;
         orc_step_tile(p, dx, u, n_in, &r, unew, NULL, cnt);
@@ -961,13 +1119,24 @@ void orc_grid_run(const orc_params *p, const double dx[3], double *u, const int 
                         if (p->physics == ORC_MHD)
                             u[PSI * G.P + c] = u[PSI * G.P + c] * r.damp;
                     }
-            continue;
+        } else {
+            for (int z = 0; z < G.n[2]; z++)
+                for (int y = 0; y < G.n[1]; y++)
+                    for (int x = 0; x < G.n[0]; x++)
+                        for (int k = 0; k < nv; k++)
+                            u[k * G.P + at(&G, x, y, z)] =
+                                unew[k * G.I + interior_index(&G, x, y, z)];
         }
-        for (int z = 0; z < G.n[2]; z++)
-            for (int y = 0; y < G.n[1]; y++)
-                for (int x = 0; x < G.n[0]; x++)
-                    for (int k = 0; k < nv; k++)
-                        u[k * G.P + at(&G, x, y, z)] = unew[k * G.I + interior_index(&G, x, y, z)];
+        /* conduction subcycle (Sec. 3.4): only the energy changes; each
+         * sub-step sees boundaries refreshed from the previous one */
+        for (int i = 0; i < r.nsub; i++) {
+            orc_grid_fill(p, u, n_in, bc);
+            orc_conduct_tile(p, dx, u, n_in, r.dt_sub, unew, NULL);
+            for (int z = 0; z < G.n[2]; z++)
+                for (int y = 0; y < G.n[1]; y++)
+                    for (int x = 0; x < G.n[0]; x++)
+                        u[EN * G.P + at(&G, x, y, z)] = unew[interior_index(&G, x, y, z)];
+        }
     }
     orc_grid_fill(p, u, n_in, bc);
     free(unew);
@@ -1313,7 +1482,15 @@ void orc_amr_cfl(orc_amr *A, orc_dtrec *out)
                 alpha = m;
         }
         sim_dxmin(A, s, &dxmin);
-        orc_make_dtrec(&A->p, alpha, dxmin, &out[s]);
+        double kmax = 0.0;
+        for (int b = 0; b < A->nb; b++) {
+            if (A->keys[b].sim != s || A->haskids[b])
+                continue;
+            double k = orc_tile_cond_rate(&A->p, tile(A, b), nn);
+            if (k > kmax)
+                kmax = k;
+        }
+        orc_make_dtrec(&A->p, alpha, dxmin, kmax, &out[s]);
     }
 }
 
@@ -1515,9 +1692,63 @@ void orc_amr_totals(const orc_amr *A, double *out)
     }
 }
 
+/* the conduction subcycle of one step (Sec. 3.4, Fig. 1): sub-step i
+ * updates the energy of every leaf of each simulation with i < nsub, then
+ * the boundary procedure for the energy: reflux with the sub-step dt,
+ * restriction, exchange and prolongation (the other variables are unchanged,
+ * so refilling them is harmless). */
+void orc_amr_conduct(orc_amr *A, const orc_dtrec *dt)
+{
+    geo *G = &A->G;
+    int nn[3] = {A->n, A->n, A->n};
+    int maxsub = 0;
+    for (int s = 0; s < A->nsims; s++)
+        if (dt[s].nsub > maxsub)
+            maxsub = dt[s].nsub;
+    if (maxsub == 0)
+        return;
+    double *enew = malloc(sizeof(double) * (size_t)A->nb * G->I);
+    orc_dtrec *sub = malloc(sizeof(orc_dtrec) * A->nsims);
+    size_t nff = (size_t)2 * A->nd * A->nv * A->T;
+    for (int i = 0; i < maxsub; i++) {
+        for (int s = 0; s < A->nsims; s++) {
+            sub[s] = dt[s];
+            sub[s].dt = i < dt[s].nsub ? dt[s].dt_sub : 0.0;
+        }
+        for (int b = 0; b < A->nb; b++) {
+            double *ff = A->ff + (size_t)b * nff;
+            if (A->haskids[b])
+                continue;
+            if (sub[A->keys[b].sim].dt == 0.0) {
+                memset(ff, 0, sizeof(double) * nff);
+                continue;
+            }
+            double dx[3];
+            block_dx(A, b, dx);
+            orc_conduct_tile(&A->p, dx, tile(A, b), nn, sub[A->keys[b].sim].dt,
+                             enew + (size_t)b * G->I, ff);
+        }
+        for (int b = 0; b < A->nb; b++) {
+            if (A->haskids[b] || sub[A->keys[b].sim].dt == 0.0)
+                continue;
+            double *u = tile(A, b);
+            for (int z = 0; z < G->n[2]; z++)
+                for (int y = 0; y < G->n[1]; y++)
+                    for (int x = 0; x < G->n[0]; x++)
+                        u[EN * G->P + at(G, x, y, z)] =
+                            enew[(size_t)b * G->I + interior_index(G, x, y, z)];
+        }
+        orc_amr_reflux(A, sub);
+        orc_amr_restrict(A);
+        orc_amr_fill(A);
+    }
+    free(enew);
+    free(sub);
+}
+
 /* one cycle per step: dt, update of all leaves, reflux, restriction, then
  * ghost exchange and prolongation (the main loop of Fig. 1 with the boundary
- * work moved after the update). */
+ * work moved after the update), then the conduction subcycle. */
 void orc_amr_run(orc_amr *A, int nsteps, orc_dtrec *trace)
 {
     orc_dtrec *r = malloc(sizeof(orc_dtrec) * A->nsims);
@@ -1529,6 +1760,7 @@ void orc_amr_run(orc_amr *A, int nsteps, orc_dtrec *trace)
         orc_amr_reflux(A, r);
         orc_amr_restrict(A);
         orc_amr_fill(A);
+        orc_amr_conduct(A, r);
     }
     free(r);
 }

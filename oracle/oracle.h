@@ -28,6 +28,7 @@ enum { ORC_MINMOD = 0, ORC_VANLEER = 1, ORC_PAPER_PHI = 2 };
 enum { ORC_GLM_PAPER = 0, ORC_GLM_FASTSPEED = 1 };
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
 enum { ORC_RUSANOV = 0, ORC_HLLC = 1 };
+enum { ORC_COND_OFF = 0, ORC_COND_ISO = 1, ORC_COND_FIELD = 2 };
 
 typedef struct {
     int ndim;          /* 2 or 3 */
@@ -37,12 +38,18 @@ typedef struct {
     int glm_mode;      /* how c_h and the psi damping factor follow from dt */
     int eglm_sources;  /* 1: EGLM source terms on, 0: plain GLM */
     int riemann;       /* face flux of LF and WENO: ORC_RUSANOV or ORC_HLLC */
+    int cond_mode;     /* thermal conduction: ORC_COND_OFF, _ISO, or _FIELD (along B) */
+    int cond_max_sub;  /* at most this many conduction sub-steps per step */
     double gamma, cfl, cd, cr, eta;
+    double kappa0, kappa_exp;  /* kappa = kappa0 T^kappa_exp, T = p/rho; the
+                                  exponent is a multiple of 1/2 in [0, 5] */
     double adv[3];     /* scalar physics: constant advection velocity */
 } orc_params;
 
 typedef struct {
     double dt, ch, damp, alpha;  /* time step, GLM speed, psi factor, max speed */
+    double dt_sub;               /* conduction sub-step dt / nsub (0: no conduction) */
+    int nsub, reserved;          /* conduction sub-steps in this step */
 } orc_dtrec;
 
 typedef struct {
@@ -95,7 +102,14 @@ void orc_resistive(const orc_params *p, const double dx[3], const double *u,
 double orc_tile_maxspeed(const orc_params *p, const double *u, const int n[3]);
 /* time-step record from a max speed and the smallest cell width */
 void orc_make_dtrec(const orc_params *p, double alpha, double dxmin,
-                    orc_dtrec *out);
+                    double kmax, orc_dtrec *out);
+/* largest kappa T / p over the interior of a tile (Sec. 3.4 sub-step) */
+double orc_tile_cond_rate(const orc_params *p, const double *u, const int n[3]);
+/* one conduction sub-step on a padded tile (Sec. 3.4): enew receives the
+ * interior energy [n2][n1][n0]; ff (may be NULL) the face fluxes as in
+ * orc_step_tile (zero except the energy component) */
+void orc_conduct_tile(const orc_params *p, const double dx[3], const double *u,
+                      const int n[3], double dt_sub, double *enew, double *ff);
 
 /* ---- single uniform grid (monolithic mode): one tile covering a domain ---- */
 void orc_grid_fill(const orc_params *p, double *u, const int n[3],
@@ -120,6 +134,7 @@ void     orc_amr_cfl(orc_amr *a, orc_dtrec *out /* [nsims] */);
 void     orc_amr_step(orc_amr *a, const orc_dtrec *dt);
 void     orc_amr_reflux(orc_amr *a, const orc_dtrec *dt);
 void     orc_amr_totals(const orc_amr *a, double *out /* [nsims][nvar] */);
+void     orc_amr_conduct(orc_amr *a, const orc_dtrec *dt);  /* the conduction subcycle */
 void     orc_amr_run(orc_amr *a, int nsteps, orc_dtrec *trace /* [nsteps][nsims] or NULL */);
 void     orc_amr_counters(const orc_amr *a, long out[4]);
 

@@ -50,6 +50,10 @@ class Workload:
     scheme: str = "lf"
     limiter: str = "minmod"
     riemann: str = "rusanov"        # face flux of LF and WENO: "rusanov" or "hllc"
+    cond: str = "off"               # thermal conduction: "off", "iso", "field"
+    cond_max_sub: int = 8           # conduction sub-steps per step at most
+    kappa0: float = 0.0             # kappa = kappa0 T^kappa_exp
+    kappa_exp: float = 2.5
     glm_mode: str = "paper"
     eglm_sources: bool = True
     gamma: float = 5.0 / 3.0
