@@ -53,6 +53,7 @@ enum { MAP_BC_PERIODIC = 0, MAP_BC_OUTFLOW = 1 };
 enum { MAP_LAUNCH_BATCHED = 0, MAP_LAUNCH_PER_BLOCK = 1 };
 enum { MAP_EST_VAR = 0, MAP_EST_BMAG = 1 };
 enum { MAP_RUSANOV = 0, MAP_HLLC = 1 };
+enum { MAP_COND_OFF = 0, MAP_COND_ISO = 1, MAP_COND_FIELD = 2 };
 
 /* Scheme parameters (Sec. 2 and 3).
  *   precision     MAP_FP64: state and arithmetic in FP64.  MAP_FP32_MIXED:
@@ -76,10 +77,22 @@ enum { MAP_RUSANOV = 0, MAP_HLLC = 1 };
  *                 paper names for MHD, Sec. 3.2 and 5.2; the GLM pair takes
  *                 its exact upwind flux and the normal field its interface
  *                 value).  MMC has no Riemann solver: MAP_HLLC is MAP_EINVAL.
+ *   cond_mode     thermal conduction by a subcycle after every step (Sec. 3.4):
+ *                 MAP_COND_OFF; MAP_COND_ISO, face flux
+ *                 -sqrt(kappa_i kappa_i+1)(T_i+1 - T_i)/dx; MAP_COND_FIELD,
+ *                 the same face kappa times b_d (b . grad T) along the field
+ *                 (the form of the paper's conduction test), b = B_f/|B_f|
+ *                 with B_f the mean of the two cells' fields.  T = p/rho,
+ *                 kappa = kappa0 T^kappa_exp (kappa_exp a multiple of 1/2 in
+ *                 [0, 5]).  Sub-step limit dt_c = cfl dx_min^2 /
+ *                 (n_dim max(kappa T/p)); the step is capped at
+ *                 cond_max_sub dt_c (1..64) and split into
+ *                 nsub = ceil(dt/dt_c) equal sub-steps.
  *   eta           uniform resistivity (0 = off), Sec. 3.5. */
 typedef struct {
-    int ndim, precision, scheme, limiter, glm_mode, eglm_sources, riemann;
-    double gamma, cfl, glm_cd, glm_cr, eta;
+    int ndim, precision, scheme, limiter, glm_mode, eglm_sources, riemann, cond_mode,
+        cond_max_sub;
+    double gamma, cfl, glm_cd, glm_cr, eta, kappa0, kappa_exp;
 } map_params;
 
 /* One simulation: domain box, base-level blocks per dimension, boundary kind
@@ -97,9 +110,12 @@ typedef struct {
 } map_block_key;
 
 /* Per-simulation time-step record: dt, GLM speed c_h, psi damping factor
- * and the global maximum speed alpha_g (Sec. 2 and Sec. 3.7). */
+ * and the global maximum speed alpha_g (Sec. 2 and Sec. 3.7); with
+ * conduction, the sub-step dt_sub = dt / nsub and the number of sub-steps
+ * (both 0 without conduction). */
 typedef struct {
-    double dt, ch, damp, alpha;
+    double dt, ch, damp, alpha, dt_sub;
+    int nsub, reserved;
 } map_dt;
 
 typedef struct {
@@ -188,6 +204,16 @@ map_status map_step(map_ctx *ctx, const void *U_in, void *U_out, const map_dt *d
  * mean of the fine fluxes (Sec. 4.3 step 2).  Run after map_step. */
 map_status map_reflux(map_ctx *ctx, void *U, const map_dt *dt_dev, void *stream);
 
+/* The thermal-conduction subcycle of one step (Sec. 3.4), with the records
+ * dt_dev that map_cfl_dt wrote for the step: nsub sub-steps of length dt_sub
+ * per simulation, each advancing the energy of every leaf by the conduction
+ * scheme of params.cond_mode and then refluxing, restricting, exchanging and
+ * prolongating the energy.  The other variables do not change.  Run after the
+ * step's reflux, restriction and ghost fill (map_advance and map_graph_run
+ * do so); a no-op when conduction is off.  Uses the workspace's shadow state
+ * as scratch.  Errors: MAP_EINVAL (null or workspace-overlapping U). */
+map_status map_conduct(map_ctx *ctx, void *U, const map_dt *dt_dev, void *stream);
+
 /* FP64 volume-weighted totals of the conserved variables over the leaves of
  * each simulation, totals_dev[nsims][9] (device), fixed reduction order. */
 map_status map_totals(map_ctx *ctx, const void *U, double *totals_dev, void *stream);
@@ -201,7 +227,8 @@ map_status map_status_flags(map_ctx *ctx, uint64_t counters[4], void *stream);
 
 /* nsteps full cycles: cfl_dt, step, reflux, restrict, then the ghosts the
  * next step reads from a block's own tile (copies into the frames of the
- * parents that feed prolongation, prolongation level by level), with dt
+ * parents that feed prolongation, prolongation level by level), then the
+ * conduction subcycle when params.cond_mode is on (map_conduct), with dt
  * kept on the device (the record of the last step is copied to dt_dev if it
  * is not NULL).  LF and MMC cycles alternate between U and the workspace's
  * shadow state, and an odd nsteps ends with one device copy back into U;

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmap.so")
 SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step2.hip", "k_step3.hip", "k_step_mmc.hip",
-           "k_aux.hip", "k_regrid.hip"]
+           "k_aux.hip", "k_regrid.hip", "k_cond.hip"]
 ARCH = os.environ.get("MAP_OFFLOAD_ARCH", "gfx950")
 
 

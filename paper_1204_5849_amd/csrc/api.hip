@@ -56,10 +56,13 @@ bool fp64(const map_ctx *c) { return c->p.precision == MAP_FP64; }
 // fine).  `all`: the copies fill every slot's ghost frame; otherwise only
 // the frames the prolongation reads (the step reads same-level neighbour
 // interiors in place).
-map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all)
+map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all, int eonly_sub = -1)
 {
     FillArgs a{};
     a.U = U;
+    a.dt = dptr<map_dt>(c, c->ws.dt);
+    a.eonly = eonly_sub >= 0;
+    a.sub = eonly_sub;
     a.desc = dptr<Desc>(c, c->ws.desc);
     a.blk = dptr<BlockRec>(c, c->ws.blocks);
     a.parent = dptr<int32_t>(c, c->ws.parent);
@@ -90,11 +93,15 @@ map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all)
     return MAP_OK;
 }
 
-map_status run_restrict(map_ctx *c, void *U, hipStream_t s)
+map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1)
 {
     RestrictArgs a{};
     a.U = U;
     a.children = dptr<int32_t>(c, c->ws.children);
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.dt = dptr<map_dt>(c, c->ws.dt);
+    a.eonly = eonly_sub >= 0;
+    a.sub = eonly_sub;
     for (int l = c->lmax - 1; l >= 1; l--) {
         int lo = c->restrict_off[l], hi = c->restrict_off[l + 1];
         if (hi <= lo)
@@ -112,21 +119,28 @@ map_status run_cfl(map_ctx *c, const void *U, map_dt *dt_out, hipStream_t s)
     a.U = U;
     a.cnt = dptr<unsigned long long>(c, c->ws.counters);
     a.gamma = c->p.gamma;
+    const bool cond = c->p.cond_mode != MAP_COND_OFF;
+    a.kappa0 = c->p.kappa0;
+    a.khalf = (int)(2.0 * c->p.kappa_exp + 0.5);
     if (c->launch_mode == MAP_LAUNCH_PER_BLOCK) {
         for (int i = 0; i < c->nleaves; i++) {
             a.leaves = dptr<int32_t>(c, c->ws.leaves) + i;
             a.nleaves = 1;
             a.part = dptr<double>(c, c->ws.cfl_part) + i;
+            a.cpart = cond ? dptr<double>(c, c->ws.cond_part) + i : nullptr;
             HIPCHK(launch_cfl(c->nd, fp64(c), a, s));
         }
     } else {
         a.leaves = dptr<int32_t>(c, c->ws.leaves);
         a.nleaves = c->nleaves;
         a.part = dptr<double>(c, c->ws.cfl_part);
+        a.cpart = cond ? dptr<double>(c, c->ws.cond_part) : nullptr;
         HIPCHK(launch_cfl(c->nd, fp64(c), a, s));
     }
     DtArgs d{};
     d.part = dptr<double>(c, c->ws.cfl_part);
+    d.cpart = cond ? dptr<double>(c, c->ws.cond_part) : nullptr;
+    d.cond_max_sub = c->p.cond_max_sub;
     d.sims = dptr<SimRec>(c, c->ws.sims);
     d.dt_int = dptr<map_dt>(c, c->ws.dt);
     d.dt_out = dt_out;
@@ -207,11 +221,13 @@ map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, h
     return run_step_kernel(c, SCH_WENO2, S1, Uout, Uin, dt, s);
 }
 
-map_status run_reflux(map_ctx *c, void *U, const map_dt *dt, hipStream_t s)
+map_status run_reflux(map_ctx *c, void *U, const map_dt *dt, hipStream_t s, int eonly_sub = -1)
 {
     if (c->reflux_slots.empty())
         return MAP_OK;
     RefluxArgs a{};
+    a.eonly = eonly_sub >= 0;
+    a.sub = eonly_sub;
     a.U = U;
     a.slots = dptr<int32_t>(c, c->ws.reflux_slots);
     a.start = dptr<int32_t>(c, c->ws.reflux_start);
@@ -225,8 +241,56 @@ map_status run_reflux(map_ctx *c, void *U, const map_dt *dt, hipStream_t s)
     return MAP_OK;
 }
 
+// the conduction subcycle of one step (Sec. 3.4, Fig. 1) with the records
+// in dt (the device copy the kernels read); `scratch` is a whole state buffer
+// whose contents are dead (its T, kappa and energy planes are used):
+// cond_max_sub sub-steps are
+// launched, and every pass skips the blocks of simulations whose own count
+// nsub is smaller, so the launch sequence does not depend on device data
+// (a captured graph replays it).  Each sub-step: T and kappa, the energy
+// update into the shadow, commit, then reflux, restriction, exchange and
+// prolongation of the energy alone.
+map_status run_conduct(map_ctx *c, void *U, void *scratch, const map_dt *dt, hipStream_t s)
+{
+    if (c->p.cond_mode == MAP_COND_OFF)
+        return MAP_OK;
+    map_status st;
+    CondArgs a{};
+    a.U = U;
+    a.S = scratch;
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.desc = dptr<Desc>(c, c->ws.desc);
+    a.dt = dt;
+    a.lvl_dx = dptr<double>(c, c->ws.lvl_dx);
+    a.fbidx = dptr<int32_t>(c, c->ws.fbidx);
+    a.fbuf = c->wsp + c->ws.fbuf;
+    a.gamma = c->p.gamma;
+    a.kappa0 = c->p.kappa0;
+    a.khalf = (int)(2.0 * c->p.kappa_exp + 0.5);
+    a.mode = c->p.cond_mode;
+    for (int i = 0; i < c->p.cond_max_sub; i++) {
+        a.sub = i;
+        a.list = nullptr;
+        a.nitems = c->nslots;
+        HIPCHK(launch_cond_prep(c->nd, fp64(c), a, s));
+        a.list = dptr<int32_t>(c, c->ws.leaves);
+        a.nitems = c->nleaves;
+        HIPCHK(launch_conduct(c->nd, fp64(c), a, s));
+        HIPCHK(launch_cond_commit(c->nd, fp64(c), a, s));
+        if ((st = run_reflux(c, U, dt, s, i)) != MAP_OK)
+            return st;
+        if ((st = run_restrict(c, U, s, i)) != MAP_OK)
+            return st;
+        if ((st = run_fill(c, U, s, false, i)) != MAP_OK)
+            return st;
+    }
+    return MAP_OK;
+}
+
 // one cycle from Uin to Uout (Fig. 1): dt, update of every leaf, reflux,
-// restriction, and the ghosts the next update reads from its own tile
+// restriction, the ghosts the next update reads from its own tile, and the
+// conduction subcycle when it is on (its scratch: Uin, dead after the
+// update, or the shadow when the cycle runs in place)
 map_status run_cycle(map_ctx *c, const void *Uin, void *Uout, hipStream_t s)
 {
     map_dt *dt = dptr<map_dt>(c, c->ws.dt);
@@ -239,7 +303,10 @@ map_status run_cycle(map_ctx *c, const void *Uin, void *Uout, hipStream_t s)
         return st;
     if ((st = run_restrict(c, Uout, s)) != MAP_OK)
         return st;
-    return run_fill(c, Uout, s, false);
+    if ((st = run_fill(c, Uout, s, false)) != MAP_OK)
+        return st;
+    void *scratch = Uin != Uout ? const_cast<void *>(Uin) : shadow(c);
+    return run_conduct(c, Uout, scratch, dt, s);
 }
 
 size_t state_bytes(const map_ctx *c) { return (size_t)c->nslots * NV * c->tile * c->word; }
@@ -478,6 +545,19 @@ map_status map_reflux(map_ctx *c, void *U, const map_dt *dt_dev, void *stream)
     if (!U || !dt_dev)
         return fail(MAP_EINVAL, "null U or dt");
     return run_reflux(c, U, dt_dev, S(stream));
+}
+
+map_status map_conduct(map_ctx *c, void *U, const map_dt *dt_dev, void *stream)
+{
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U || !dt_dev)
+        return fail(MAP_EINVAL, "null U or dt");
+    const char *u0 = static_cast<const char *>(U), *w0 = c->wsp;
+    if (u0 < w0 + c->ws.total && w0 < u0 + state_bytes(c))
+        return fail(MAP_EINVAL, "U overlaps the bound workspace");
+    return run_conduct(c, U, shadow(c), dt_dev, S(stream));
 }
 
 map_status map_totals(map_ctx *c, const void *U, double *totals_dev, void *stream)

@@ -71,11 +71,25 @@ __device__ __forceinline__ void ghost_xyz(int g, int &x, int &y, int &z)
     }
 }
 
+// variables a pass moves: all, or the energy alone (EO, conduction sub-steps)
+template <bool EO>
+struct VarRange {
+    static constexpr int K0 = EO ? EN : 0, K1 = EO ? EN + 1 : NV;
+};
+
+// a conduction sub-step pass skips the blocks of simulations whose subcycle
+// has fewer sub-steps
+__device__ __forceinline__ bool sub_inactive(const map_dt *dt, int sim, int sub)
+{
+    return sub >= dt[sim].nsub;
+}
+
 // ---- same-level copies and physical edges (descriptor src >= 0)
-template <int NDIM, typename T>
+template <int NDIM, typename T, bool EO>
 __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
 {
     constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC, BPW = FG<NDIM>::BPW;
+    constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     T *U = (T *)a.U;
     int first, stride, end;
     xcd_range(a.nitems, first, stride, end);
@@ -86,6 +100,8 @@ __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
             if (i >= a.slot_end)
                 break;
             const int slot = a.copy_list ? a.copy_list[i] : i;
+            if (EO && sub_inactive(a.dt, a.blk[slot].sim, a.sub))
+                continue;
             int x, y, z;
             ghost_xyz<NDIM>(gi, x, y, z);
             const Desc ds = a.desc[(size_t)slot * NDIR + dir_index<NDIM>(x, y, z)];
@@ -97,10 +113,10 @@ __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
             const T *src = U + (size_t)ds.src * NV * P + lin<NDIM>(sx, sy, sz);
             T v[NV];
 #pragma unroll
-            for (int k = 0; k < NV; k++)
+            for (int k = K0; k < K1; k++)
                 v[k] = src[(size_t)k * P];
 #pragma unroll
-            for (int k = 0; k < NV; k++)
+            for (int k = K0; k < K1; k++)
                 dst[(size_t)k * P] = v[k];
         }
     }
@@ -108,7 +124,7 @@ __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
 
 // minmod-limited linear interpolation from the parent's padded tile at fine
 // padded cell (x, y, z) of a child in position cpos (Sec. 4.3, step 6)
-template <int NDIM, typename T>
+template <int NDIM, typename T, int K0 = 0, int K1 = NV>
 __device__ __forceinline__ void prolong_cell(const T *pu, int cpos, int x, int y, int z, T out[NV])
 {
     constexpr int P = FG<NDIM>::P;
@@ -124,7 +140,7 @@ __device__ __forceinline__ void prolong_cell(const T *pu, int cpos, int x, int y
     const int c = lin<NDIM>(ci[0], ci[1], ci[2]);
     const int st[3] = {1, PD, PD * PD};
 #pragma unroll
-    for (int k = 0; k < NV; k++) {
+    for (int k = K0; k < K1; k++) {
         const T *q = pu + (size_t)k * P;
         T val = q[c];
         T v = val;
@@ -138,15 +154,18 @@ __device__ __forceinline__ void prolong_cell(const T *pu, int cpos, int x, int y
 }
 
 // ---- prolongated ghosts of the blocks of one level (descriptor src == -1)
-template <int NDIM, typename T>
+template <int NDIM, typename T, bool EO>
 __global__ void __launch_bounds__(NTA) k_prolong_ghosts(FillArgs a)
 {
     constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC;
+    constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     T *U = (T *)a.U;
     int first, stride, end;
     xcd_range(a.nitems, first, stride, end);  // siblings share the parent tile in L2
     for (int item = first; item < end; item += stride) {
         const int slot = a.list[item];
+        if (EO && sub_inactive(a.dt, a.blk[slot].sim, a.sub))
+            continue;
         const int par = a.parent[slot];
         const int cpos = a.blk[slot].cpos;
         const T *pu = U + (size_t)par * NV * P;
@@ -158,10 +177,10 @@ __global__ void __launch_bounds__(NTA) k_prolong_ghosts(FillArgs a)
             if (ds.src != -1)
                 continue;
             T v[NV];
-            prolong_cell<NDIM, T>(pu, cpos, x, y, z, v);
+            prolong_cell<NDIM, T, K0, K1>(pu, cpos, x, y, z, v);
             const int c = lin<NDIM>(x, y, z);
 #pragma unroll
-            for (int k = 0; k < NV; k++)
+            for (int k = K0; k < K1; k++)
                 ub[(size_t)k * P + c] = v[k];
         }
     }
@@ -193,7 +212,6 @@ __global__ void __launch_bounds__(NTA) k_prolong_blocks(FillArgs a)
     }
 }
 
-// ---- restriction: parent cell = pairwise mean of its 2^d fine cells
 // ---- restriction: parent interior = mean of the 2^d child cells it covers
 // (Sec. 4.2, Sec. 4.3 step 1); one workgroup per parent.  The two cells of
 // an x pair are adjacent and 2-element aligned in the padded tile, so each
@@ -209,14 +227,17 @@ struct Pair<double> {
     using V = double2;
 };
 
-template <int NDIM, typename T>
+template <int NDIM, typename T, bool EO>
 __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
 {
     using V = typename Pair<T>::V;
     constexpr int P = FG<NDIM>::P, NI = FG<NDIM>::NI;
+    constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     T *U = (T *)a.U;
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         const int slot = a.list[item];
+        if (EO && sub_inactive(a.dt, a.blk[slot].sim, a.sub))
+            continue;
         T *ub = U + (size_t)slot * NV * P;
         for (int i = threadIdx.x; i < NI; i += NTA) {
             const int X = i % NB, Y = (i / NB) % NB, Z = NDIM == 3 ? i / (NB * NB) : 0;
@@ -226,7 +247,7 @@ __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
             const int lx = fx % NB, ly = fy % NB, lz = NDIM == 3 ? fz % NB : 0;
             const int c0 = lin<NDIM>(lx, ly, lz);
 #pragma unroll
-            for (int k = 0; k < NV; k++) {
+            for (int k = K0; k < K1; k++) {
                 const T *q = cu + (size_t)k * P + c0;
                 const V r0 = *reinterpret_cast<const V *>(q);
                 const V r1 = *reinterpret_cast<const V *>(q + PD);
@@ -246,25 +267,28 @@ __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
 }
 
 // ---- reflux: one workgroup per coarse leaf, its faces in a fixed order
-template <int NDIM, typename T>
+template <int NDIM, typename T, bool EO>
 __global__ void __launch_bounds__(NTA) k_reflux(RefluxArgs a)
 {
     constexpr int P = FG<NDIM>::P;
     constexpr int FC = NDIM == 3 ? NB * NB : NB;
+    constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     T *U = (T *)a.U;
     const T *fb = (const T *)a.fbuf;
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         const int slot = a.slots[item];
         const BlockRec br = a.blk[slot];
-        const double dtv = a.dt[br.sim].dt;
+        if (EO && sub_inactive(a.dt, br.sim, a.sub))
+            continue;
+        const double dtv = EO ? a.dt[br.sim].dt_sub : a.dt[br.sim].dt;
         const double *dxp = a.lvl_dx + ((size_t)br.sim * (MAXL + 1) + br.level) * 3;
         T *ub = U + (size_t)slot * NV * P;
         for (int e = a.start[item]; e < a.start[item + 1]; e++) {
             const RefluxRec r = a.recs[e];
             const T dtdx = (T)(dtv / dxp[r.dim]);
             const int t1 = r.dim == 0 ? 1 : 0, t2 = r.dim == 2 ? 1 : 2;
-            for (int idx = threadIdx.x; idx < FC * NV; idx += NTA) {
-                const int k = idx / FC, tt = idx - k * FC;
+            for (int idx = threadIdx.x; idx < FC * (K1 - K0); idx += NTA) {
+                const int k = K0 + idx / FC, tt = idx - (k - K0) * FC;
                 const int ta = tt % NB, tb = NDIM == 3 ? tt / NB : 0;
                 T f[4];
                 const int nf = NDIM == 3 ? 4 : 2;
@@ -308,7 +332,7 @@ __global__ void __launch_bounds__(NTA) k_cfl(CflArgs a)
     for (int item = blockIdx.x; item < a.nleaves; item += gridDim.x) {
         const int slot = a.leaves[item];
         const T *ub = U + (size_t)slot * NV * P;
-        double m = 0.0;
+        double m = 0.0, cm = 0.0;
         unsigned bad = 0, nonfin = 0;
         for (int i = threadIdx.x; i < NI; i += NTA) {
             const int x = i % NB, y = (i / NB) % NB, z = NDIM == 3 ? i / (NB * NB) : 0;
@@ -332,6 +356,11 @@ __global__ void __launch_bounds__(NTA) k_cfl(CflArgs a)
             const double pr = (a.gamma - 1.0) * (u[EN] - ke - 0.5 * bb);
             if (!(u[RHO] > 0.0) || !(pr > 0.0))
                 bad++;
+            if (a.cpart) {
+                // conduction: kappa T / p = kappa / rho with T = p / rho
+                const double r = kappa_of(a.kappa0, a.khalf, pr / u[RHO]) / u[RHO];
+                cm = r > cm ? r : cm;
+            }
             const double a2 = a.gamma * pr * ir, sab = a2 + bb * ir;
             auto fast = [&](double vd, double Bd) {
                 double disc = sab * sab - 4.0 * a2 * (Bd * Bd) * ir;
@@ -354,22 +383,30 @@ __global__ void __launch_bounds__(NTA) k_cfl(CflArgs a)
         if (nonfin)
             atomicAdd(&a.cnt[3], (unsigned long long)nonfin);
         // wave64 shuffle max, then across the 4 waves through LDS
+        auto block_max = [&](double v) {
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            double o = __shfl_xor(m, off, 64);
-            m = o > m ? o : m;
-        }
-        const int w = threadIdx.x >> 6;
-        if ((threadIdx.x & 63) == 0)
-            red[w] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
+            for (int off = 32; off > 0; off >>= 1) {
+                double o = __shfl_xor(v, off, 64);
+                v = o > v ? o : v;
+            }
+            const int w = threadIdx.x >> 6;
+            if ((threadIdx.x & 63) == 0)
+                red[w] = v;
+            __syncthreads();
             double r = red[0];
             for (int i = 1; i < NTA / 64; i++)
                 r = red[i] > r ? red[i] : r;
-            a.part[item] = r;
+            __syncthreads();
+            return r;
+        };
+        const double mm = block_max(m);
+        if (threadIdx.x == 0)
+            a.part[item] = mm;
+        if (a.cpart) {
+            const double cc = block_max(cm);
+            if (threadIdx.x == 0)
+                a.cpart[item] = cc;
         }
-        __syncthreads();
     }
 }
 
@@ -381,21 +418,27 @@ __global__ void __launch_bounds__(NTA) k_dt(DtArgs a)
     if (s >= a.nsims)
         return;
     const SimRec sr = a.sims[s];
-    double m = 0.0;
-    for (int i = sr.leaf_lo + (int)threadIdx.x; i < sr.leaf_hi; i += NTA)
-        m = a.part[i] > m ? a.part[i] : m;
+    auto sim_max = [&](const double *part) {
+        double m = 0.0;
+        for (int i = sr.leaf_lo + (int)threadIdx.x; i < sr.leaf_hi; i += NTA)
+            m = part[i] > m ? part[i] : m;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        double o = __shfl_xor(m, off, 64);
-        m = o > m ? o : m;
-    }
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double alpha = red[0];
+        for (int off = 32; off > 0; off >>= 1) {
+            double o = __shfl_xor(m, off, 64);
+            m = o > m ? o : m;
+        }
+        if ((threadIdx.x & 63) == 0)
+            red[threadIdx.x >> 6] = m;
+        __syncthreads();
+        double r = red[0];
         for (int i = 1; i < NTA / 64; i++)
-            alpha = red[i] > alpha ? red[i] : alpha;
+            r = red[i] > r ? red[i] : r;
+        __syncthreads();
+        return r;
+    };
+    const double alpha = sim_max(a.part);
+    const double kmax = a.cpart ? sim_max(a.cpart) : 0.0;
+    if (threadIdx.x == 0) {
         const double dxmin = sr.dxmin;
         double dt = a.cfl * dxmin / (a.ndim * alpha);
         if (a.eta > 0.0) {
@@ -403,6 +446,20 @@ __global__ void __launch_bounds__(NTA) k_dt(DtArgs a)
             dt = dr < dt ? dr : dt;
         }
         map_dt r;
+        r.dt_sub = 0.0;
+        r.nsub = 0;
+        r.reserved = 0;
+        if (a.cpart && kmax > 0.0) {
+            // conduction sub-step limit (Sec. 3.4); the step holds at most
+            // cond_max_sub sub-steps
+            const double dtc = a.cfl * dxmin * dxmin / (a.ndim * kmax);
+            const double cap = a.cond_max_sub * dtc;
+            dt = cap < dt ? cap : dt;
+            const double ns = ceil(dt / dtc);
+            const int nsub = ns < 1.0 ? 1 : (ns > a.cond_max_sub ? a.cond_max_sub : (int)ns);
+            r.nsub = nsub;
+            r.dt_sub = dt / nsub;
+        }
         r.dt = dt;
         r.alpha = alpha;
         if (a.glm_mode == MAP_GLM_PAPER) {
@@ -533,6 +590,36 @@ __global__ void k_clear_u64(unsigned long long *p, int n)
         }                                                                           \
     } while (0)
 
+// as DISPATCH, for kernels with an energy-only variant chosen by a.eonly
+#define DISPATCH_EO(ndim, fp64, eo, KER, ...)                                       \
+    do {                                                                            \
+        if (eo) {                                                                   \
+            if (ndim == 2) {                                                        \
+                if (fp64)                                                           \
+                    hipLaunchKernelGGL((KER<2, double, true>), __VA_ARGS__);        \
+                else                                                                \
+                    hipLaunchKernelGGL((KER<2, float, true>), __VA_ARGS__);         \
+            } else {                                                                \
+                if (fp64)                                                           \
+                    hipLaunchKernelGGL((KER<3, double, true>), __VA_ARGS__);        \
+                else                                                                \
+                    hipLaunchKernelGGL((KER<3, float, true>), __VA_ARGS__);         \
+            }                                                                       \
+        } else {                                                                    \
+            if (ndim == 2) {                                                        \
+                if (fp64)                                                           \
+                    hipLaunchKernelGGL((KER<2, double, false>), __VA_ARGS__);       \
+                else                                                                \
+                    hipLaunchKernelGGL((KER<2, float, false>), __VA_ARGS__);        \
+            } else {                                                                \
+                if (fp64)                                                           \
+                    hipLaunchKernelGGL((KER<3, double, false>), __VA_ARGS__);       \
+                else                                                                \
+                    hipLaunchKernelGGL((KER<3, float, false>), __VA_ARGS__);        \
+            }                                                                       \
+        }                                                                           \
+    } while (0)
+
 int fill_blocks_per_group(int ndim) { return ndim == 3 ? FG<3>::BPW : FG<2>::BPW; }
 
 hipError_t launch_fill_copy(int ndim, bool fp64, const FillArgs &a, int grid, hipStream_t s)
@@ -540,7 +627,7 @@ hipError_t launch_fill_copy(int ndim, bool fp64, const FillArgs &a, int grid, hi
     if (a.nitems <= 0)
         return hipSuccess;
     const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
-    DISPATCH(ndim, fp64, k_fill_copy, dim3(g), dim3(NTA), 0, s, a);
+    DISPATCH_EO(ndim, fp64, a.eonly, k_fill_copy, dim3(g), dim3(NTA), 0, s, a);
     return hipGetLastError();
 }
 
@@ -548,7 +635,7 @@ hipError_t launch_prolong_ghosts(int ndim, bool fp64, const FillArgs &a, hipStre
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    DISPATCH(ndim, fp64, k_prolong_ghosts, dim3(a.nitems), dim3(NTA), 0, s, a);
+    DISPATCH_EO(ndim, fp64, a.eonly, k_prolong_ghosts, dim3(a.nitems), dim3(NTA), 0, s, a);
     return hipGetLastError();
 }
 
@@ -564,7 +651,7 @@ hipError_t launch_restrict(int ndim, bool fp64, const RestrictArgs &a, hipStream
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    DISPATCH(ndim, fp64, k_restrict, dim3(a.nitems), dim3(NTA), 0, s, a);
+    DISPATCH_EO(ndim, fp64, a.eonly, k_restrict, dim3(a.nitems), dim3(NTA), 0, s, a);
     return hipGetLastError();
 }
 
@@ -572,7 +659,7 @@ hipError_t launch_reflux(int ndim, bool fp64, const RefluxArgs &a, hipStream_t s
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    DISPATCH(ndim, fp64, k_reflux, dim3(a.nitems), dim3(NTA), 0, s, a);
+    DISPATCH_EO(ndim, fp64, a.eonly, k_reflux, dim3(a.nitems), dim3(NTA), 0, s, a);
     return hipGetLastError();
 }
 

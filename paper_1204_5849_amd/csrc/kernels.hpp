@@ -31,6 +31,8 @@ struct StepArgs {
     int eglm, limiter, riemann;
 };
 
+// energy-only passes of a conduction sub-step (eonly = 1): only the energy
+// moves, and blocks of simulations with sub >= dt[sim].nsub are skipped
 struct FillArgs {
     void *U;
     const Desc *desc;
@@ -39,6 +41,8 @@ struct FillArgs {
     const int32_t *list;       // prolongation: slots of the launch
     const int32_t *copy_list;  // copies: slots (null: slot = index)
     int slot_base, slot_end, nitems;  // copies: index range [slot_base, slot_end)
+    const map_dt *dt;
+    int eonly, sub;
 };
 
 struct RestrictArgs {
@@ -46,6 +50,9 @@ struct RestrictArgs {
     const int32_t *list;
     const int32_t *children;
     int nitems;
+    const BlockRec *blk;
+    const map_dt *dt;
+    int eonly, sub;
 };
 
 struct RefluxArgs {
@@ -58,6 +65,7 @@ struct RefluxArgs {
     const double *lvl_dx;
     const void *fbuf;
     int nitems;
+    int eonly, sub;  // conduction sub-step: energy only, dt_sub
 };
 
 struct CflArgs {
@@ -65,17 +73,36 @@ struct CflArgs {
     const int32_t *leaves;
     int nleaves;
     double *part;
+    double *cpart;  // conduction: per leaf max kappa T / p (null: off)
     unsigned long long *cnt;
-    double gamma;
+    double gamma, kappa0;
+    int khalf;      // 2 x kappa exponent
 };
 
 struct DtArgs {
     const double *part;
+    const double *cpart;  // null: no conduction
     const SimRec *sims;
     map_dt *dt_int;
     map_dt *dt_out;  // optional copy
-    int nsims, ndim, glm_mode;
+    int nsims, ndim, glm_mode, cond_max_sub;
     double cfl, cd, cr, eta;
+};
+
+// one conduction sub-step (Sec. 3.4)
+struct CondArgs {
+    void *U;
+    void *S;               // workspace shadow: T and kappa planes, new energy plane
+    const int32_t *list;   // prep: every slot (null: index); conduct / commit: leaves
+    int nitems;
+    const BlockRec *blk;
+    const Desc *desc;
+    const map_dt *dt;
+    const double *lvl_dx;
+    const int32_t *fbidx;
+    void *fbuf;
+    double gamma, kappa0;
+    int khalf, mode, sub;
 };
 
 struct TotalsArgs {
@@ -126,6 +153,9 @@ hipError_t launch_prim_to_cons(bool fp64, void *U, size_t ncell_per_var_total, i
                                double gamma, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_estimate(int ndim, bool fp64, const EstArgs &a, hipStream_t s);
+hipError_t launch_cond_prep(int ndim, bool fp64, const CondArgs &a, hipStream_t s);
+hipError_t launch_conduct(int ndim, bool fp64, const CondArgs &a, hipStream_t s);
+hipError_t launch_cond_commit(int ndim, bool fp64, const CondArgs &a, hipStream_t s);
 hipError_t launch_remap_copy(const RemapArgs &a, hipStream_t s);
 
 }  // namespace mapk

@@ -48,7 +48,7 @@ struct SimRec {
 struct WsLayout {
     size_t blocks, desc, parent, children, fbidx, leaves, restrict_list, prolong_list,
         frame_list, reflux_slots, reflux_start, reflux_recs, sims, lvl_dx, dt, cfl_part,
-        tot_part, counters, fbuf, remap, newlist, shadow, total;
+        cond_part, tot_part, counters, fbuf, remap, newlist, shadow, total;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

@@ -29,6 +29,18 @@ struct Num<float> {
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 };
 
+// conduction coefficient kappa = kappa0 T^(khalf/2) (Sec. 3.4): whole
+// powers by repeated multiplication, then one square root for a half power
+__device__ __forceinline__ double kappa_of(double kappa0, int khalf, double T)
+{
+    double q = 1.0;
+    for (int i = 0; i < khalf / 2; i++)
+        q = q * T;
+    if (khalf & 1)
+        q = q * sqrt(T);
+    return kappa0 * q;
+}
+
 template <typename T>
 __device__ __forceinline__ T sgn_of(T a)
 {

@@ -91,6 +91,20 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
         err = "MMC uses Lax-Friedrichs splitting, not a Riemann solver";
         return MAP_EINVAL;
     }
+    if (p->cond_mode != MAP_COND_OFF && p->cond_mode != MAP_COND_ISO &&
+        p->cond_mode != MAP_COND_FIELD) {
+        err = "unknown cond_mode";
+        return MAP_EINVAL;
+    }
+    if (p->cond_mode != MAP_COND_OFF) {
+        const double h2 = 2.0 * p->kappa_exp;
+        if (p->cond_max_sub < 1 || p->cond_max_sub > 64 || !(p->kappa0 >= 0.0) ||
+            !(h2 >= 0.0 && h2 <= 10.0) || h2 != (double)(int)h2) {
+            err = "conduction needs 1 <= cond_max_sub <= 64, kappa0 >= 0 and kappa_exp a "
+                  "multiple of 1/2 in [0, 5]";
+            return MAP_EINVAL;
+        }
+    }
     if (nsims >= (1 << 15)) {
         err = "too many simulations";
         return MAP_EINVAL;
@@ -464,6 +478,7 @@ void map_plan_layout(map_ctx *c)
     L.lvl_dx = take(c->lvl_dx.size() * sizeof(double));
     L.dt = take(ns * sizeof(map_dt));
     L.cfl_part = take((size_t)c->nleaves * sizeof(double));
+    L.cond_part = take((size_t)c->nleaves * sizeof(double));
     L.tot_part = take((size_t)c->nleaves * NV * sizeof(double));
     L.counters = take(4 * sizeof(unsigned long long));
     L.fbuf = take((size_t)c->nfb * NV * c->face_cells() * c->word);

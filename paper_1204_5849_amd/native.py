@@ -21,6 +21,7 @@ MAP_BC_PERIODIC, MAP_BC_OUTFLOW = 0, 1
 MAP_LAUNCH_BATCHED, MAP_LAUNCH_PER_BLOCK = 0, 1
 MAP_EST_VAR, MAP_EST_BMAG = 0, 1
 MAP_RUSANOV, MAP_HLLC = 0, 1
+MAP_COND_OFF, MAP_COND_ISO, MAP_COND_FIELD = 0, 1, 2
 
 SCHEMES = {"lf": MAP_LF, "mmc": MAP_MMC, "weno": MAP_WENO}
 LIMITERS = {"minmod": MAP_MINMOD, "vanleer": MAP_VANLEER, "paper": MAP_PAPER_PHI}
@@ -28,10 +29,11 @@ GLM = {"paper": MAP_GLM_PAPER, "fastspeed": MAP_GLM_FASTSPEED}
 BC = {"periodic": MAP_BC_PERIODIC, "outflow": MAP_BC_OUTFLOW}
 PRECISION = {"fp64": MAP_FP64, "fp32": MAP_FP32_MIXED}
 RIEMANN = {"rusanov": MAP_RUSANOV, "hllc": MAP_HLLC}
+COND = {"off": MAP_COND_OFF, "iso": MAP_COND_ISO, "field": MAP_COND_FIELD}
 
 EXPORTS = ["map_init_blocks", "map_query", "map_neighbors", "map_bind_workspace",
            "map_prim_to_cons", "map_fill_ghosts", "map_restrict", "map_prolong", "map_cfl_dt",
-           "map_step", "map_reflux", "map_totals", "map_status_flags", "map_advance",
+           "map_step", "map_reflux", "map_conduct", "map_totals", "map_status_flags", "map_advance",
            "map_graph_run", "map_set_launch", "map_autotune", "map_estimate", "map_regrid",
            "map_remap", "map_last_error", "map_destroy"]
 
@@ -45,9 +47,10 @@ class MapError(RuntimeError):
 class map_params(C.Structure):
     _fields_ = [("ndim", C.c_int), ("precision", C.c_int), ("scheme", C.c_int),
                 ("limiter", C.c_int), ("glm_mode", C.c_int), ("eglm_sources", C.c_int),
-                ("riemann", C.c_int), ("gamma", C.c_double), ("cfl", C.c_double),
-                ("glm_cd", C.c_double),
-                ("glm_cr", C.c_double), ("eta", C.c_double)]
+                ("riemann", C.c_int), ("cond_mode", C.c_int), ("cond_max_sub", C.c_int),
+                ("gamma", C.c_double), ("cfl", C.c_double), ("glm_cd", C.c_double),
+                ("glm_cr", C.c_double), ("eta", C.c_double), ("kappa0", C.c_double),
+                ("kappa_exp", C.c_double)]
 
 
 class map_sim_desc(C.Structure):
@@ -62,7 +65,11 @@ class map_block_key(C.Structure):
 
 class map_dt(C.Structure):
     _fields_ = [("dt", C.c_double), ("ch", C.c_double), ("damp", C.c_double),
-                ("alpha", C.c_double)]
+                ("alpha", C.c_double), ("dt_sub", C.c_double), ("nsub", C.c_int),
+                ("reserved", C.c_int)]
+
+
+DT_WORDS = C.sizeof(map_dt) // 8  # float64 words per record
 
 
 class map_sizes(C.Structure):
@@ -107,6 +114,7 @@ def lib():
         L.map_cfl_dt.argtypes = [vp, vp, vp, vp]
         L.map_step.argtypes = [vp, vp, vp, vp, vp]
         L.map_reflux.argtypes = [vp, vp, vp, vp]
+        L.map_conduct.argtypes = [vp, vp, vp, vp]
         L.map_totals.argtypes = [vp, vp, vp, vp]
         L.map_status_flags.argtypes = [vp, C.POINTER(C.c_uint64), vp]
         L.map_advance.argtypes = [vp, vp, vp, C.c_int, vp]
@@ -146,7 +154,7 @@ def _p(x):
 # ---------------------------------------------------------------- thin wrappers
 def make_params(ndim, precision="fp64", scheme="lf", limiter="minmod", glm_mode="paper",
                 eglm_sources=True, gamma=5.0 / 3.0, cfl=0.4, cd=0.18, cr=0.18, eta=0.0,
-                riemann="rusanov"):
+                riemann="rusanov", cond="off", cond_max_sub=8, kappa0=0.0, kappa_exp=2.5):
     p = map_params()
     p.ndim = ndim
     p.precision = PRECISION.get(precision, precision)
@@ -155,6 +163,9 @@ def make_params(ndim, precision="fp64", scheme="lf", limiter="minmod", glm_mode=
     p.glm_mode = GLM.get(glm_mode, glm_mode)
     p.eglm_sources = int(bool(eglm_sources))
     p.riemann = RIEMANN.get(riemann, riemann)
+    p.cond_mode = COND.get(cond, cond)
+    p.cond_max_sub = cond_max_sub
+    p.kappa0, p.kappa_exp = kappa0, kappa_exp
     p.gamma, p.cfl, p.glm_cd, p.glm_cr, p.eta = gamma, cfl, cd, cr, eta
     return p
 
@@ -233,6 +244,10 @@ def map_step(ctx, Uin, Uout, dt_dev, stream):
 
 def map_reflux(ctx, U, dt_dev, stream):
     check(lib().map_reflux(ctx, _p(U), _p(dt_dev), _p(stream)))
+
+
+def map_conduct(ctx, U, dt_dev, stream):
+    check(lib().map_conduct(ctx, _p(U), _p(dt_dev), _p(stream)))
 
 
 def map_totals(ctx, U, out_dev, stream):

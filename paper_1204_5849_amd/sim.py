@@ -28,6 +28,8 @@ class Simulation:
         self.dtype = torch.float64 if self.precision == "fp64" else torch.float32
         self.params = N.make_params(wl.ndim, precision=self.precision, scheme=wl.scheme,
                                     limiter=wl.limiter, glm_mode=wl.glm_mode, riemann=wl.riemann,
+                                    cond=wl.cond, cond_max_sub=wl.cond_max_sub, kappa0=wl.kappa0,
+                                    kappa_exp=wl.kappa_exp,
                                     eglm_sources=wl.eglm_sources, gamma=wl.gamma, cfl=wl.cfl,
                                     cd=wl.cd, cr=wl.cr, eta=wl.eta)
         self.ctx = N.map_init_blocks(self.params, wl.sims, wl.keys)
@@ -41,7 +43,7 @@ class Simulation:
             self.U = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
             self.ws = torch.zeros(self.sizes.workspace_bytes + 256, dtype=torch.uint8,
                                   device=self.device)
-            self.dt = torch.zeros((len(wl.sims), 4), dtype=torch.float64, device=self.device)
+            self.dt = torch.zeros((len(wl.sims), N.DT_WORDS), dtype=torch.float64, device=self.device)
         torch.cuda.synchronize(self.device)
         base = self.ws.data_ptr()
         self._ws_ptr = (base + 255) & ~255
@@ -115,6 +117,10 @@ class Simulation:
 
     def reflux(self):
         N.map_reflux(self.ctx, self.U, self.dt, self.sp)
+
+    def conduct(self):
+        """The conduction subcycle of one step with the current dt records."""
+        N.map_conduct(self.ctx, self.U, self.dt, self.sp)
 
     def totals(self) -> np.ndarray:
         out = torch.zeros((len(self.wl.sims), NV), dtype=torch.float64, device=self.device)

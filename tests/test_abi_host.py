@@ -45,6 +45,14 @@ def _sims2d(nb=(2, 2, 1), bc="periodic"):
     return [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb, bc=((bc, bc),) * 3)]
 
 
+def test_every_export_has_declared_argument_types():
+    """Without declared argument types ctypes passes Python ints as 32-bit C
+    ints, which would truncate device and stream pointers."""
+    L = N.lib()
+    for name in N.EXPORTS:
+        assert getattr(L, name).argtypes is not None, name
+
+
 def test_tree_errors():
     p = N.make_params(2)
     sims = _sims2d()

@@ -1,0 +1,159 @@
+"""GPU parity of the thermal-conduction subcycle (Sec. 3.4 of the paper)
+through the C ABI against the FP64 oracle: FP64 relative L-infinity per
+variable <= 1e-11 over whole cycles (update, boundary procedure and the
+subcycle with its energy-only reflux, restriction and fill), the sub-step
+records, the subcycle alone (map_conduct), conservation, uniform states and
+the cycle forms (graph, eager, per-block; odd and even cycle counts)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1204_5849_amd import native as N  # noqa: E402
+from paper_1204_5849_amd import workloads as W  # noqa: E402
+from tests.helpers import random_tree  # noqa: E402
+from tests.test_gpu_parity import TOL64, _check, _leaf_interiors, _say, _sim  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    N.lib()  # fails loudly if libmap.so is missing
+    return "cuda:0"
+
+
+def _hot_ic(wl, sim, lv, x, y, z, g):
+    zero = 0.0 * x
+    tp = 2 * np.pi
+    rho = np.where((np.abs(x - 0.5) < 0.15) & (np.abs(y - 0.5) < 0.15), 0.05, 0.1) + zero
+    # every component of natural size, so that relative errors are meaningful
+    return [rho, 0.05 * np.sin(tp * y), 0.05 * np.cos(tp * x), 0.03 * np.sin(tp * (x + y)),
+            1.0 + 0.2 * np.sin(tp * y), 0.8 + zero, 0.1 + zero, 0.1 + zero, zero]
+
+
+def _workload(ndim, cond, scheme="lf", bc="periodic", seed=0, precision="fp64", **kw):
+    rng = np.random.default_rng(300 + seed + ndim)
+    nb = (2, 2, 1) if ndim == 2 else (2, 2, 2)
+    bcs = ((bc, bc),) * 3 if bc != "mixed" else (("periodic",) * 2, ("outflow",) * 2, ("periodic",) * 2)
+    sims = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb, bc=bcs)]
+    keys = random_tree(sims, ndim, 3, 0.4, rng)
+    return W.Workload(name="cond", ndim=ndim, sims=sims, keys=keys, ic=_hot_ic, scheme=scheme,
+                      cond=cond, kappa0=kw.get("kappa0", 0.01), kappa_exp=2.5,
+                      cond_max_sub=kw.get("max_sub", 5), precision=precision,
+                      eglm_sources=kw.get("eglm", True))
+
+
+def _run_both(w, nsteps):
+    import oracle as orc
+    s = _sim(w)
+    A = orc.load_workload(w)
+    recs = []
+    for _ in range(nsteps):
+        r = A.cfl()[0]
+        recs.append((r.dt, r.dt_sub, r.nsub, r.ch))
+        A.run(1)
+        s.advance(1)
+    s.sync()
+    return s, A, recs
+
+
+@pytest.mark.parametrize("ndim,cond,scheme,bc", [(2, "iso", "lf", "periodic"),
+                                                 (2, "field", "weno", "outflow"),
+                                                 (3, "field", "lf", "mixed"),
+                                                 (3, "iso", "weno", "periodic")])
+def test_cycles_with_conduction_fp64(dev, ndim, cond, scheme, bc):
+    _say(f"conduction cycles ndim={ndim} {cond} {scheme} bc={bc}")
+    w = _workload(ndim, cond, scheme, bc, seed=len(cond))
+    s, A, recs = _run_both(w, 3)
+    assert max(r[2] for r in recs) >= 2
+    dt = s.dt.cpu()
+    assert int(dt[0].view(torch.int32)[10]) == recs[-1][2]  # nsub of the last step
+    np.testing.assert_allclose(float(dt[0, 4]), recs[-1][1], rtol=1e-11)
+    _check(w, s.state_by_key(), A.state, TOL64, f"conduction {cond} {scheme} 3 cycles",
+           ch=[recs[-1][3]])
+
+
+def test_subcycle_alone_fp64(dev):
+    """map_conduct with the step's records equals the oracle's subcycle."""
+    import oracle as orc
+    _say("map_conduct alone, 3-D field-aligned")
+    w = _workload(3, "field", seed=7)
+    s = _sim(w)
+    A = orc.load_workload(w)
+    s.cfl()
+    s.conduct()
+    r = A.cfl()
+    orc.lib().orc_amr_conduct(A.h, (orc.DtRec * 1)(r[0]))
+    s.sync()
+    assert r[0].nsub >= 2
+    _check(w, s.state_by_key(), A.state, TOL64, "subcycle alone", ch=[r[0].ch])
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_conduction_conserves_energy(dev, ndim):
+    """Plain GLM, periodic tree: the eight MHD totals stay constant over
+    whole cycles with the subcycle (reflux of the conduction fluxes)."""
+    _say(f"conduction conservation ndim={ndim}")
+    w = _workload(ndim, "field", seed=11, eglm=False)
+    s = _sim(w)
+    t0 = s.totals()
+    s.graph_run(4)
+    t1 = s.totals()
+    scale = np.abs(_leaf_interiors(w, s.state_by_key())).max(axis=(0, 2, 3, 4))
+    assert np.all(np.abs(t1[0, :8] - t0[0, :8]) <= 1e-13 * scale[:8]), t1 - t0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_uniform_state_with_conduction_bitwise(dev, precision):
+    _say(f"uniform state with conduction {precision}")
+    w = _workload(3, "field", bc="mixed", seed=3, precision=precision)
+    w.ic = lambda wl, s, lv, x, y, z, g: [1.2, 0.3, -0.2, 0.1, 0.4, 0.5, -0.6, 0.9, 0.0]
+    w.kappa0 = 1.0
+    s = _sim(w)
+    u0 = s.U.clone()
+    s.graph_run(2)
+    s.advance(1)
+    s.fill()
+    s.sync()
+    assert torch.equal(s.U, u0)
+
+
+def test_graph_equals_eager_and_per_block_with_conduction(dev):
+    """The LF cycle alternates U and the shadow and uses the dead input as
+    the subcycle's scratch: graph and eager runs, odd and even counts, and
+    per-block launches give the same state bit for bit."""
+    _say("conduction graph vs eager vs per-block")
+    w = _workload(2, "field", seed=5)
+    a, b, c = _sim(w), _sim(w), _sim(w, launch="per_block")
+    a.advance(3)
+    b.graph_run(3)
+    c.advance(3)
+    for x in (a, b, c):
+        x.fill()
+    ua = a.state_by_key()
+    assert np.array_equal(ua, b.state_by_key())
+    assert np.array_equal(ua, c.state_by_key())
+    a.advance(2)
+    b.graph_run(2)
+    a.fill()
+    b.fill()
+    assert np.array_equal(a.state_by_key(), b.state_by_key())
+
+
+def test_conduction_fp32_l1_vs_fp64_oracle(dev):
+    import oracle as orc
+    _say("conduction fp32 vs fp64 oracle, 2-D field, WENO, 4 cycles")
+    w = _workload(2, "field", "weno", seed=9, precision="fp32")
+    s = _sim(w)
+    A = orc.load_workload(w)
+    s.advance(4)
+    A.run(4)
+    g = _leaf_interiors(w, s.state_by_key())
+    o = _leaf_interiors(w, A.state)
+    for k, nm in ((0, "rho"), (7, "e")):
+        e = np.abs(g[:, k] - o[:, k]).mean() / np.abs(o[:, k]).mean()
+        _say(f"  {nm} rel L1 {e:.2e}")
+        assert e <= 1e-4

@@ -104,7 +104,7 @@ def test_cfl_record_matches(dev, orc):
     A = orc.load_workload(w)
     s.cfl()
     s.sync()
-    rec = s.dt.cpu().numpy()[0]
+    rec = s.dt.cpu().numpy()[0][:4]
     r = A.cfl()[0]
     np.testing.assert_allclose(rec, [r.dt, r.ch, r.damp, r.alpha], rtol=1e-14)
 
@@ -157,7 +157,7 @@ def test_amr_resistive_3d_fp64(dev):
     _say("harris 3d small, eta, fastspeed GLM, 4 steps")
     w = W.harris3d(nbase=2, levels=3, precision="fp64")
     s, A, tr, dts = _run_both(w, 4)
-    np.testing.assert_allclose(dts[:, 0], tr[:, 0], rtol=1e-12)
+    np.testing.assert_allclose(dts[:, 0, :4], tr[:, 0], rtol=1e-12)
     _check(w, s.state_by_key(), A.state, TOL64, "harris small 4 steps", ch=tr[-1, :, 1])
 
 
