@@ -11,6 +11,8 @@ Also reported on the same workload and initial data:
   * whole WENO + TVD Runge-Kutta 2 cycles (Sec. 3.3), with the Rusanov and
     with the HLLC face flux, their rates and the time of one two-stage
     update;
+  * whole LF cycles with the thermal-conduction subcycle (Sec. 3.4) along the
+    field, their rate and the time per sub-step;
   * the FP64 path launched once per block ("plain"), its rate and the
     relative L1 distance of the FP32 result from it after the same steps;
   * roofline of the dominant kernel (the step kernel), timed with HIP events
@@ -291,6 +293,42 @@ def time_weno(wl, precision, steps, autotune=True, riemann="rusanov"):
     return out_d
 
 
+def time_conduction(wl, precision, steps, plain_ms, autotune=True):
+    """Whole LF cycles with the conduction subcycle along the field (Sec. 3.4;
+    Spitzer kappa = kappa0 T^(5/2), kappa0 = 0.4, at most 8 sub-steps) on the
+    same blocks and data, captured in a HIP graph; the subcycle's share is the
+    cycle time above the plain cycle's, per sub-step."""
+    import dataclasses
+    import torch
+    from paper_1204_5849_amd import native as N
+    from paper_1204_5849_amd.sim import Simulation
+    ww = dataclasses.replace(wl, cond="field", kappa0=0.4, kappa_exp=2.5, cond_max_sub=8)
+    sim = Simulation(ww, precision=precision)
+    sim.load_initial()
+    if autotune:
+        sim.autotune()
+    sim.graph_run(2)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.graph_run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    nsub = int(sim.dt[0].cpu().view(torch.int32)[10])
+    st, cnt = sim.flags()
+    ms = el / steps * 1e3
+    out = {"ms_per_step": ms, "value": ww.n_leaf_cells() * steps / el, "unit": "cell-updates/s",
+           "steps": steps, "nsub_last_step": nsub, "max_sub": ww.cond_max_sub,
+           "kappa0": ww.kappa0, "kappa_exp": ww.kappa_exp, "mode": "field",
+           "subcycle_ms_per_substep": (ms - plain_ms) / max(nsub, 1),
+           "flags": [int(c) for c in cnt],
+           "note": "LF + minmod + Rusanov with the conduction subcycle after every step; "
+                   "inactive sub-steps (index >= nsub) exit at once"}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def rel_l1(a, b):
     return float(np.abs(a - b).mean() / max(np.abs(b).mean(), 1e-300))
 
@@ -306,6 +344,7 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-regrid", action="store_true")
     ap.add_argument("--no-weno", action="store_true")
+    ap.add_argument("--no-cond", action="store_true")
     ap.add_argument("--weno-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -423,6 +462,14 @@ def main():
         r = result["weno_hllc"]
         log(f"weno+hllc: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.3f} G cell-updates/s, "
             f"map_step {r['step_ms']:.3f} ms")
+
+    if not args.no_cond:
+        log("LF cycles with the conduction subcycle on the same workload")
+        result["conduction"] = time_conduction(wl, args.precision, args.weno_steps, ms,
+                                               not args.no_autotune)
+        r = result["conduction"]
+        log(f"conduction: {r['ms_per_step']:.3f} ms/step with {r['nsub_last_step']} sub-steps, "
+            f"{r['subcycle_ms_per_substep']:.3f} ms per sub-step")
 
     if not args.no_plain:
         log("FP64 plain per-block path on the same workload")

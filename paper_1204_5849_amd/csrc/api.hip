@@ -243,13 +243,13 @@ map_status run_reflux(map_ctx *c, void *U, const map_dt *dt, hipStream_t s, int 
 
 // the conduction subcycle of one step (Sec. 3.4, Fig. 1) with the records
 // in dt (the device copy the kernels read); `scratch` is a whole state buffer
-// whose contents are dead (its T, kappa and energy planes are used):
+// whose contents are dead (its energy plane takes the new energy):
 // cond_max_sub sub-steps are
 // launched, and every pass skips the blocks of simulations whose own count
 // nsub is smaller, so the launch sequence does not depend on device data
-// (a captured graph replays it).  Each sub-step: T and kappa, the energy
-// update into the shadow, commit, then reflux, restriction, exchange and
-// prolongation of the energy alone.
+// (a captured graph replays it).  Each sub-step: the energy update into the
+// scratch, commit, then reflux, restriction, exchange and prolongation of the
+// energy alone.
 map_status run_conduct(map_ctx *c, void *U, void *scratch, const map_dt *dt, hipStream_t s)
 {
     if (c->p.cond_mode == MAP_COND_OFF)
@@ -268,13 +268,10 @@ map_status run_conduct(map_ctx *c, void *U, void *scratch, const map_dt *dt, hip
     a.kappa0 = c->p.kappa0;
     a.khalf = (int)(2.0 * c->p.kappa_exp + 0.5);
     a.mode = c->p.cond_mode;
+    a.list = dptr<int32_t>(c, c->ws.leaves);
+    a.nitems = c->nleaves;
     for (int i = 0; i < c->p.cond_max_sub; i++) {
         a.sub = i;
-        a.list = nullptr;
-        a.nitems = c->nslots;
-        HIPCHK(launch_cond_prep(c->nd, fp64(c), a, s));
-        a.list = dptr<int32_t>(c, c->ws.leaves);
-        a.nitems = c->nleaves;
         HIPCHK(launch_conduct(c->nd, fp64(c), a, s));
         HIPCHK(launch_cond_commit(c->nd, fp64(c), a, s));
         if ((st = run_reflux(c, U, dt, s, i)) != MAP_OK)

@@ -92,8 +92,8 @@ struct DtArgs {
 // one conduction sub-step (Sec. 3.4)
 struct CondArgs {
     void *U;
-    void *S;               // workspace shadow: T and kappa planes, new energy plane
-    const int32_t *list;   // prep: every slot (null: index); conduct / commit: leaves
+    void *S;               // scratch state: its energy plane takes the new energy
+    const int32_t *list;   // leaves
     int nitems;
     const BlockRec *blk;
     const Desc *desc;
@@ -153,7 +153,6 @@ hipError_t launch_prim_to_cons(bool fp64, void *U, size_t ncell_per_var_total, i
                                double gamma, hipStream_t s);
 hipError_t launch_clear_u64(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_estimate(int ndim, bool fp64, const EstArgs &a, hipStream_t s);
-hipError_t launch_cond_prep(int ndim, bool fp64, const CondArgs &a, hipStream_t s);
 hipError_t launch_conduct(int ndim, bool fp64, const CondArgs &a, hipStream_t s);
 hipError_t launch_cond_commit(int ndim, bool fp64, const CondArgs &a, hipStream_t s);
 hipError_t launch_remap_copy(const RemapArgs &a, hipStream_t s);
