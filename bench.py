@@ -286,7 +286,7 @@ def time_weno(wl, precision, steps, autotune=True, riemann="rusanov"):
     out_d = {"riemann": riemann, "ms_per_step": el / steps * 1e3, "value": cells * steps / el, "unit": "cell-updates/s",
              "steps": steps, "step_ms": t_step * 1e3, "flags": [int(c) for c in cnt],
              "flops_per_cell_update_stages": [f1, f2],
-             "note": "stage kernels k_step3/k_step2 <..., 1|2, 0>; per-stage durations in the "
+             "note": "stage kernels k_step3/k_step2 <..., 1|2, 0, flux>, flux 0 Rusanov, 1 HLLC; per-stage durations in the "
                      "kernel-trace summary"}
     del out, sim
     torch.cuda.empty_cache()
