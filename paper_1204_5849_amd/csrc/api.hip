@@ -93,7 +93,9 @@ map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all, int eonly_sub 
     return MAP_OK;
 }
 
-map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1)
+// restriction of every parent, finest level first; with cfl, the leaf
+// children's CFL maxima into the per-leaf parts as well
+map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1, bool cfl = false)
 {
     RestrictArgs a{};
     a.U = U;
@@ -102,6 +104,11 @@ map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1)
     a.dt = dptr<map_dt>(c, c->ws.dt);
     a.eonly = eonly_sub >= 0;
     a.sub = eonly_sub;
+    a.cfl = cfl;
+    a.part = dptr<double>(c, c->ws.cfl_part);
+    a.leaf_of = dptr<int32_t>(c, c->ws.leaf_of);
+    a.cnt = dptr<unsigned long long>(c, c->ws.counters);
+    a.gamma = c->p.gamma;
     for (int l = c->lmax - 1; l >= 1; l--) {
         int lo = c->restrict_off[l], hi = c->restrict_off[l + 1];
         if (hi <= lo)
@@ -113,7 +120,32 @@ map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1)
     return MAP_OK;
 }
 
-map_status run_cfl(map_ctx *c, const void *U, map_dt *dt_out, hipStream_t s)
+// the dt records of every simulation from the per-leaf parts into dt_int
+// (the first record buffer if null) and, if given, dt_out
+map_status run_dt(map_ctx *c, map_dt *dt_out, hipStream_t s, map_dt *dt_int = nullptr)
+{
+    const bool cond = c->p.cond_mode != MAP_COND_OFF;
+    DtArgs d{};
+    d.part = dptr<double>(c, c->ws.cfl_part);
+    d.cpart = cond ? dptr<double>(c, c->ws.cond_part) : nullptr;
+    d.cond_max_sub = c->p.cond_max_sub;
+    d.sims = dptr<SimRec>(c, c->ws.sims);
+    d.dt_int = dt_int ? dt_int : dptr<map_dt>(c, c->ws.dt);
+    d.dt_out = dt_out;
+    d.nsims = (int)c->sims.size();
+    d.ndim = c->nd;
+    d.glm_mode = c->p.glm_mode;
+    d.cfl = c->p.cfl;
+    d.cd = c->p.glm_cd;
+    d.cr = c->p.glm_cr;
+    d.eta = c->p.eta;
+    HIPCHK(launch_dt(d, s));
+    return MAP_OK;
+}
+
+// the per-leaf CFL parts of every leaf of U, then the dt records
+map_status run_cfl(map_ctx *c, const void *U, map_dt *dt_out, hipStream_t s,
+                   map_dt *dt_int = nullptr)
 {
     CflArgs a{};
     a.U = U;
@@ -137,22 +169,25 @@ map_status run_cfl(map_ctx *c, const void *U, map_dt *dt_out, hipStream_t s)
         a.cpart = cond ? dptr<double>(c, c->ws.cond_part) : nullptr;
         HIPCHK(launch_cfl(c->nd, fp64(c), a, s));
     }
-    DtArgs d{};
-    d.part = dptr<double>(c, c->ws.cfl_part);
-    d.cpart = cond ? dptr<double>(c, c->ws.cond_part) : nullptr;
-    d.cond_max_sub = c->p.cond_max_sub;
-    d.sims = dptr<SimRec>(c, c->ws.sims);
-    d.dt_int = dptr<map_dt>(c, c->ws.dt);
-    d.dt_out = dt_out;
-    d.nsims = (int)c->sims.size();
-    d.ndim = c->nd;
-    d.glm_mode = c->p.glm_mode;
-    d.cfl = c->p.cfl;
-    d.cd = c->p.glm_cd;
-    d.cr = c->p.glm_cr;
-    d.eta = c->p.eta;
-    HIPCHK(launch_dt(d, s));
-    return MAP_OK;
+    return run_dt(c, dt_out, s, dt_int);
+}
+
+// after a restriction that formed the parts of every leaf with a parent:
+// the parts of the leaves without one, then the dt records into dt_int
+map_status run_cfl_rest(map_ctx *c, const void *U, hipStream_t s, map_dt *dt_int)
+{
+    if (!c->orphans.empty()) {
+        CflArgs a{};
+        a.U = U;
+        a.cnt = dptr<unsigned long long>(c, c->ws.counters);
+        a.gamma = c->p.gamma;
+        a.leaves = dptr<int32_t>(c, c->ws.orphans);
+        a.nleaves = (int)c->orphans.size();
+        a.part = dptr<double>(c, c->ws.cfl_part);
+        a.part_idx = dptr<int32_t>(c, c->ws.orphan_idx);
+        HIPCHK(launch_cfl(c->nd, fp64(c), a, s));
+    }
+    return run_dt(c, nullptr, s, dt_int);
 }
 
 // one launch of the block-update kernel of the scheme (for WENO: one stage)
@@ -284,27 +319,38 @@ map_status run_conduct(map_ctx *c, void *U, void *scratch, const map_dt *dt, hip
     return MAP_OK;
 }
 
-// one cycle from Uin to Uout (Fig. 1): dt, update of every leaf, reflux,
-// restriction, the ghosts the next update reads from its own tile, and the
-// conduction subcycle when it is on (its scratch: Uin, dead after the
-// update, or the shadow when the cycle runs in place)
-map_status run_cycle(map_ctx *c, const void *Uin, void *Uout, hipStream_t s)
+// one cycle from Uin to Uout (Fig. 1) with the dt records `dt` (formed here
+// from Uin if need_cfl): update of every leaf, reflux, restriction, the
+// ghosts the next update reads from its own tile, and the conduction
+// subcycle when it is on (its scratch: Uin, dead after the update, or the
+// shadow when the cycle runs in place).  With `next`, the next cycle's dt
+// records are formed into `next` on the way: the restriction takes the CFL
+// maxima of the leaves with a parent from the values it reads (final after
+// reflux), a small pass those of the leaves without one.
+map_status run_cycle(map_ctx *c, const void *Uin, void *Uout, hipStream_t s, map_dt *dt,
+                     bool need_cfl, map_dt *next)
 {
-    map_dt *dt = dptr<map_dt>(c, c->ws.dt);
     map_status st;
-    if ((st = run_cfl(c, Uin, nullptr, s)) != MAP_OK)
+    if (need_cfl && (st = run_cfl(c, Uin, nullptr, s, dt)) != MAP_OK)
         return st;
     if ((st = run_step(c, Uin, Uout, dt, s)) != MAP_OK)
         return st;
     if ((st = run_reflux(c, Uout, dt, s)) != MAP_OK)
         return st;
-    if ((st = run_restrict(c, Uout, s)) != MAP_OK)
+    if ((st = run_restrict(c, Uout, s, -1, next != nullptr)) != MAP_OK)
         return st;
     if ((st = run_fill(c, Uout, s, false)) != MAP_OK)
+        return st;
+    if (next && (st = run_cfl_rest(c, Uout, s, next)) != MAP_OK)
         return st;
     void *scratch = Uin != Uout ? const_cast<void *>(Uin) : shadow(c);
     return run_conduct(c, Uout, scratch, dt, s);
 }
+
+// the next cycle's dt can come from this one only if the leaf interiors are
+// final after the restriction: not with the conduction subcycle, which
+// changes the energy after the fill
+bool chain_dt(const map_ctx *c) { return c->p.cond_mode == MAP_COND_OFF; }
 
 size_t state_bytes(const map_ctx *c) { return (size_t)c->nslots * NV * c->tile * c->word; }
 
@@ -312,23 +358,36 @@ void *shadow(map_ctx *c) { return c->wsp + c->ws.shadow; }
 
 // n cycles alternating between U and the workspace's shadow state; an odd
 // count ends with one copy of the shadow back into U.  WENO cycles run in
-// place (the shadow holds the Runge-Kutta stage).
+// place (the shadow holds the Runge-Kutta stage).  The first cycle forms its
+// dt records; each later one takes those the cycle before formed, the two
+// alternating between the two record buffers.
 map_status run_cycles(map_ctx *c, void *U, int n, hipStream_t s)
 {
     map_status st;
-    if (c->p.scheme == MAP_WENO) {
-        for (int i = 0; i < n; i++)
-            if ((st = run_cycle(c, U, U, s)) != MAP_OK)
-                return st;
-        return MAP_OK;
-    }
+    const bool chain = chain_dt(c);
+    const size_t off[2] = {c->ws.dt, c->ws.dt2};
+    int cur = 0;
+    bool need = true;
     void *S2 = shadow(c);
     for (int i = 0; i < n; i++) {
-        const bool even = (i & 1) == 0;
-        if ((st = run_cycle(c, even ? U : S2, even ? S2 : U, s)) != MAP_OK)
+        void *in = U, *out = U;
+        if (c->p.scheme != MAP_WENO) {
+            const bool even = (i & 1) == 0;
+            in = even ? U : S2;
+            out = even ? S2 : U;
+        }
+        map_dt *next = chain && i + 1 < n ? dptr<map_dt>(c, off[cur ^ 1]) : nullptr;
+        if ((st = run_cycle(c, in, out, s, dptr<map_dt>(c, off[cur]), need, next)) != MAP_OK)
             return st;
+        c->last_dt = off[cur];
+        if (next) {
+            cur ^= 1;
+            need = false;
+        } else {
+            need = true;
+        }
     }
-    if (n & 1)
+    if (c->p.scheme != MAP_WENO && (n & 1))
         HIPCHK(hipMemcpyAsync(U, S2, state_bytes(c), hipMemcpyDeviceToDevice, s));
     return MAP_OK;
 }
@@ -338,6 +397,10 @@ void drop_graph(map_ctx *c)
     if (c->graph_exec) {
         hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(c->graph_exec));
         c->graph_exec = nullptr;
+    }
+    if (c->graph_exec2) {
+        hipGraphExecDestroy(reinterpret_cast<hipGraphExec_t>(c->graph_exec2));
+        c->graph_exec2 = nullptr;
     }
     c->graph_U = nullptr;
 }
@@ -441,6 +504,9 @@ map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
     HIPCHK(up(c->ws.children, c->children.data(), c->children.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.fbidx, c->fbidx.data(), c->fbidx.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.leaves, c->leaves.data(), c->leaves.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.leaf_of, c->leaf_of.data(), c->leaf_of.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.orphans, c->orphans.data(), c->orphans.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.orphan_idx, c->orphan_idx.data(), c->orphan_idx.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.restrict_list, c->restrict_list.data(), c->restrict_list.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.prolong_list, c->prolong_list.data(), c->prolong_list.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.frame_list, c->frame_list.data(), c->frame_list.size() * sizeof(int32_t)));
@@ -452,6 +518,7 @@ map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
     HIPCHK(launch_clear_u64(dptr<unsigned long long>(c, c->ws.counters), 4, s));
     // the host vectors above are pageable: finish the copies before returning
     HIPCHK(hipStreamSynchronize(s));
+    c->last_dt = c->ws.dt;
     c->bound = true;
     return MAP_OK;
 }
@@ -511,6 +578,7 @@ map_status map_cfl_dt(map_ctx *c, const void *U, map_dt *dt_dev, void *stream)
         return st;
     if (!U)
         return fail(MAP_EINVAL, "null U");
+    c->last_dt = c->ws.dt;
     return run_cfl(c, U, dt_dev, S(stream));
 }
 
@@ -611,7 +679,7 @@ map_status map_advance(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *st
     if ((st = run_cycles(c, U, nsteps, s)) != MAP_OK)
         return st;
     if (dt_dev && nsteps > 0)
-        HIPCHK(hipMemcpyAsync(dt_dev, c->wsp + c->ws.dt, sizeof(map_dt) * c->sims.size(),
+        HIPCHK(hipMemcpyAsync(dt_dev, c->wsp + c->last_dt, sizeof(map_dt) * c->sims.size(),
                               hipMemcpyDeviceToDevice, s));
     return MAP_OK;
 }
@@ -624,6 +692,7 @@ map_status map_graph_run(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *
     if (!U || nsteps < 0)
         return fail(MAP_EINVAL, "null U or negative step count");
     hipStream_t s = S(stream);
+    const bool chain = chain_dt(c);
     if (!c->graph_exec || c->graph_U != U) {
         drop_graph(c);
         if (!c->cap_stream) {
@@ -632,35 +701,54 @@ map_status map_graph_run(map_ctx *c, void *U, map_dt *dt_dev, int nsteps, void *
             c->cap_stream = cs;
         }
         hipStream_t cs = S(c->cap_stream);
-        // two cycles, U -> shadow -> U (WENO: U -> U twice)
+        // two cycles, U -> shadow -> U (WENO: U -> U twice).  With chained
+        // dt records: the first pair of a run forms its first records, each
+        // cycle forms the next one's (the second cycle's for the next pair),
+        // and the later pairs start from those; otherwise every cycle forms
+        // its own.
         void *mid = c->p.scheme == MAP_WENO ? U : shadow(c);
-        HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
-        st = run_cycle(c, U, mid, cs);
-        if (st == MAP_OK)
-            st = run_cycle(c, mid, U, cs);
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(cs, &g);
-        if (st != MAP_OK) {
-            if (g)
-                hipGraphDestroy(g);
+        map_dt *D0 = dptr<map_dt>(c, c->ws.dt), *D1 = dptr<map_dt>(c, c->ws.dt2);
+        auto capture = [&](bool first, void **out) -> map_status {
+            HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed));
+            map_status r = chain ? run_cycle(c, U, mid, cs, D0, first, D1)
+                                 : run_cycle(c, U, mid, cs, D0, true, nullptr);
+            if (r == MAP_OK)
+                r = chain ? run_cycle(c, mid, U, cs, D1, false, D0)
+                          : run_cycle(c, mid, U, cs, D0, true, nullptr);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(cs, &g);
+            if (r != MAP_OK) {
+                if (g)
+                    hipGraphDestroy(g);
+                return r;
+            }
+            if (e != hipSuccess)
+                return fail(MAP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess)
+                return fail(MAP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            *out = ex;
+            return MAP_OK;
+        };
+        if ((st = capture(true, &c->graph_exec)) != MAP_OK)
+            return st;
+        if (chain && (st = capture(false, &c->graph_exec2)) != MAP_OK) {
+            drop_graph(c);
             return st;
         }
-        if (e != hipSuccess)
-            return fail(MAP_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-        hipGraphExec_t ex = nullptr;
-        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
-        if (e != hipSuccess)
-            return fail(MAP_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-        c->graph_exec = ex;
         c->graph_U = U;
     }
-    for (int i = 0; i + 1 < nsteps; i += 2)
-        HIPCHK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(c->graph_exec), s));
+    for (int i = 0; i + 1 < nsteps; i += 2) {
+        void *ex = chain && i > 0 ? c->graph_exec2 : c->graph_exec;
+        HIPCHK(hipGraphLaunch(reinterpret_cast<hipGraphExec_t>(ex), s));
+        c->last_dt = chain ? c->ws.dt2 : c->ws.dt;
+    }
     if ((nsteps & 1) && (st = run_cycles(c, U, 1, s)) != MAP_OK)
         return st;
     if (dt_dev && nsteps > 0)
-        HIPCHK(hipMemcpyAsync(dt_dev, c->wsp + c->ws.dt, sizeof(map_dt) * c->sims.size(),
+        HIPCHK(hipMemcpyAsync(dt_dev, c->wsp + c->last_dt, sizeof(map_dt) * c->sims.size(),
                               hipMemcpyDeviceToDevice, s));
     return MAP_OK;
 }

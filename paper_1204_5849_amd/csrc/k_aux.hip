@@ -227,25 +227,78 @@ struct Pair<double> {
     using V = double2;
 };
 
-template <int NDIM, typename T, bool EO>
+// the CFL speed of one cell (Sec. 3.7): max over d of |v_d| + c_f,d, in FP64
+// from its conserved variables; pr takes the gas pressure and bad is set
+// when rho <= 0 or p <= 0
+template <int NDIM>
+__device__ __forceinline__ double cfl_speed(const double (&u)[NV], double gamma, double &pr,
+                                            bool &bad)
+{
+    // primitives once per cell, then |v_d| + c_f,d for each d
+    const double ir = 1.0 / u[RHO];
+    const double vx = u[MX] * ir, vy = u[MY] * ir, vz = u[MZ] * ir;
+    const double ke = 0.5 * (u[MX] * vx + u[MY] * vy + u[MZ] * vz);
+    const double bb = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
+    pr = (gamma - 1.0) * (u[EN] - ke - 0.5 * bb);
+    bad = !(u[RHO] > 0.0) || !(pr > 0.0);
+    const double a2 = gamma * pr * ir, sab = a2 + bb * ir;
+    auto fast = [&](double vd, double Bd) {
+        double disc = sab * sab - 4.0 * a2 * (Bd * Bd) * ir;
+        disc = disc < 0.0 ? 0.0 : disc;
+        double cf2 = 0.5 * (sab + sqrt(disc));
+        cf2 = cf2 < 0.0 ? 0.0 : cf2;
+        return fabs(vd) + sqrt(cf2);
+    };
+    double s = fast(vx, u[BX]);
+    const double s1 = fast(vy, u[BY]);
+    s = s1 > s ? s1 : s;
+    if constexpr (NDIM == 3) {
+        const double s2 = fast(vz, u[BZ]);
+        s = s2 > s ? s2 : s;
+    }
+    return s;
+}
+
+// ---- restriction: one workgroup per parent, one parent cell per thread and
+//      pass; with CFL, the CFL maxima of the leaf children as well (the
+//      values the restriction reads are the leaves' final ones after
+//      reflux), so that the next cycle's dt needs no pass of its own over
+//      those leaves: a thread's parent cells lie in one child per half of the
+//      parent in z, each thread keeps its maxima per half, and the
+//      workgroup combines them per child with LDS atomics on the bit
+//      patterns (the speeds are finite and non-negative, so those order like
+//      the values)
+template <int NDIM, typename T, bool EO, bool CFL = false>
 __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
 {
     using V = typename Pair<T>::V;
     constexpr int P = FG<NDIM>::P, NI = FG<NDIM>::NI;
     constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
+    constexpr int NCH = NDIM == 3 ? 8 : 4, NC = NDIM == 3 ? 8 : 4;
+    static_assert(!CFL || (!EO && NTA == NB * NB), "CFL: all variables, one column per thread");
+    __shared__ unsigned long long smax[CFL ? NCH : 1];
     T *U = (T *)a.U;
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         const int slot = a.list[item];
         if (EO && sub_inactive(a.dt, a.blk[slot].sim, a.sub))
             continue;
         T *ub = U + (size_t)slot * NV * P;
+        double m[2] = {0.0, 0.0};
+        unsigned bad = 0, nonfin = 0;
+        if constexpr (CFL) {
+            if (threadIdx.x < NCH)
+                smax[threadIdx.x] = 0ull;
+            __syncthreads();
+        }
         for (int i = threadIdx.x; i < NI; i += NTA) {
             const int X = i % NB, Y = (i / NB) % NB, Z = NDIM == 3 ? i / (NB * NB) : 0;
             const int fx = 2 * X, fy = 2 * Y, fz = 2 * Z;
             const int cbit = (fx / NB) | ((fy / NB) << 1) | (NDIM == 3 ? (fz / NB) << 2 : 0);
-            const T *cu = U + (size_t)a.children[(size_t)slot * 8 + cbit] * NV * P;
+            const int child = a.children[(size_t)slot * 8 + cbit];
+            const T *cu = U + (size_t)child * NV * P;
             const int lx = fx % NB, ly = fy % NB, lz = NDIM == 3 ? fz % NB : 0;
             const int c0 = lin<NDIM>(lx, ly, lz);
+            T cv[CFL ? NV : 1][CFL ? NC : 1];  // the child cells, for the CFL speeds
 #pragma unroll
             for (int k = K0; k < K1; k++) {
                 const T *q = cu + (size_t)k * P + c0;
@@ -259,8 +312,63 @@ __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
                     const V r3 = *reinterpret_cast<const V *>(q + PD * PD + PD);
                     v = (((r0.x + r0.y) + (r1.x + r1.y)) + ((r2.x + r2.y) + (r3.x + r3.y))) *
                         T(0.125);
+                    if constexpr (CFL) {
+                        cv[k][4] = r2.x;
+                        cv[k][5] = r2.y;
+                        cv[k][6] = r3.x;
+                        cv[k][7] = r3.y;
+                    }
+                }
+                if constexpr (CFL) {
+                    cv[k][0] = r0.x;
+                    cv[k][1] = r0.y;
+                    cv[k][2] = r1.x;
+                    cv[k][3] = r1.y;
                 }
                 ub[(size_t)k * P + lin<NDIM>(X, Y, Z)] = v;
+            }
+            if constexpr (CFL) {
+                if (a.leaf_of[child] >= 0) {
+                    double &mh = m[NDIM == 3 ? fz / NB : 0];
+#pragma unroll
+                    for (int c = 0; c < NC; c++) {
+                        double u[NV];
+                        bool fin = true;
+#pragma unroll
+                        for (int k = 0; k < NV; k++) {
+                            u[k] = (double)cv[k][c];
+                            fin = fin && isfinite(u[k]);
+                        }
+                        if (!fin) {
+                            nonfin++;
+                            continue;
+                        }
+                        double pr;
+                        bool b;
+                        const double sp = cfl_speed<NDIM>(u, a.gamma, pr, b);
+                        if (b)
+                            bad++;
+                        mh = sp > mh ? sp : mh;
+                    }
+                }
+            }
+        }
+        if constexpr (CFL) {
+            // this thread's children: the one of its column below the middle
+            // in z, and (3-D) the one above it
+            const int cb = (threadIdx.x % NB >= NB / 2) | ((threadIdx.x / NB >= NB / 2) << 1);
+            atomicMax(&smax[cb], (unsigned long long)__double_as_longlong(m[0]));
+            if constexpr (NDIM == 3)
+                atomicMax(&smax[cb | 4], (unsigned long long)__double_as_longlong(m[1]));
+            if (bad)
+                atomicAdd(&a.cnt[2], (unsigned long long)bad);
+            if (nonfin)
+                atomicAdd(&a.cnt[3], (unsigned long long)nonfin);
+            __syncthreads();
+            if (threadIdx.x < NCH) {
+                const int li = a.leaf_of[a.children[(size_t)slot * 8 + threadIdx.x]];
+                if (li >= 0)
+                    a.part[li] = __longlong_as_double((long long)smax[threadIdx.x]);
             }
         }
     }
@@ -348,33 +456,15 @@ __global__ void __launch_bounds__(NTA) k_cfl(CflArgs a)
                 nonfin++;
                 continue;
             }
-            // primitives once per cell, then |v_d| + c_f,d for each d
-            const double ir = 1.0 / u[RHO];
-            const double vx = u[MX] * ir, vy = u[MY] * ir, vz = u[MZ] * ir;
-            const double ke = 0.5 * (u[MX] * vx + u[MY] * vy + u[MZ] * vz);
-            const double bb = u[BX] * u[BX] + u[BY] * u[BY] + u[BZ] * u[BZ];
-            const double pr = (a.gamma - 1.0) * (u[EN] - ke - 0.5 * bb);
-            if (!(u[RHO] > 0.0) || !(pr > 0.0))
+            double pr;
+            bool b;
+            const double s = cfl_speed<NDIM>(u, a.gamma, pr, b);
+            if (b)
                 bad++;
             if (a.cpart) {
                 // conduction: kappa T / p = kappa / rho with T = p / rho
                 const double r = kappa_of(a.kappa0, a.khalf, pr / u[RHO]) / u[RHO];
                 cm = r > cm ? r : cm;
-            }
-            const double a2 = a.gamma * pr * ir, sab = a2 + bb * ir;
-            auto fast = [&](double vd, double Bd) {
-                double disc = sab * sab - 4.0 * a2 * (Bd * Bd) * ir;
-                disc = disc < 0.0 ? 0.0 : disc;
-                double cf2 = 0.5 * (sab + sqrt(disc));
-                cf2 = cf2 < 0.0 ? 0.0 : cf2;
-                return fabs(vd) + sqrt(cf2);
-            };
-            double s = fast(vx, u[BX]);
-            const double s1 = fast(vy, u[BY]);
-            s = s1 > s ? s1 : s;
-            if constexpr (NDIM == 3) {
-                const double s2 = fast(vz, u[BZ]);
-                s = s2 > s ? s2 : s;
             }
             m = s > m ? s : m;
         }
@@ -399,13 +489,14 @@ __global__ void __launch_bounds__(NTA) k_cfl(CflArgs a)
             __syncthreads();
             return r;
         };
+        const int pi = a.part_idx ? a.part_idx[item] : item;
         const double mm = block_max(m);
         if (threadIdx.x == 0)
-            a.part[item] = mm;
+            a.part[pi] = mm;
         if (a.cpart) {
             const double cc = block_max(cm);
             if (threadIdx.x == 0)
-                a.cpart[item] = cc;
+                a.cpart[pi] = cc;
         }
     }
 }
@@ -591,6 +682,21 @@ __global__ void k_clear_u64(unsigned long long *p, int n)
     } while (0)
 
 // as DISPATCH, for kernels with an energy-only variant chosen by a.eonly
+#define DISPATCH_CFL(ndim, fp64, ...)                                               \
+    do {                                                                            \
+        if (ndim == 2) {                                                            \
+            if (fp64)                                                               \
+                hipLaunchKernelGGL((k_restrict<2, double, false, true>), __VA_ARGS__); \
+            else                                                                    \
+                hipLaunchKernelGGL((k_restrict<2, float, false, true>), __VA_ARGS__); \
+        } else {                                                                    \
+            if (fp64)                                                               \
+                hipLaunchKernelGGL((k_restrict<3, double, false, true>), __VA_ARGS__); \
+            else                                                                    \
+                hipLaunchKernelGGL((k_restrict<3, float, false, true>), __VA_ARGS__); \
+        }                                                                           \
+    } while (0)
+
 #define DISPATCH_EO(ndim, fp64, eo, KER, ...)                                       \
     do {                                                                            \
         if (eo) {                                                                   \
@@ -651,7 +757,13 @@ hipError_t launch_restrict(int ndim, bool fp64, const RestrictArgs &a, hipStream
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    DISPATCH_EO(ndim, fp64, a.eonly, k_restrict, dim3(a.nitems), dim3(NTA), 0, s, a);
+    if (a.cfl) {
+        if (a.eonly)
+            return hipErrorInvalidValue;
+        DISPATCH_CFL(ndim, fp64, dim3(a.nitems), dim3(NTA), 0, s, a);
+    } else {
+        DISPATCH_EO(ndim, fp64, a.eonly, k_restrict, dim3(a.nitems), dim3(NTA), 0, s, a);
+    }
     return hipGetLastError();
 }
 

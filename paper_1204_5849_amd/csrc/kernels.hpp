@@ -53,6 +53,14 @@ struct RestrictArgs {
     const BlockRec *blk;
     const map_dt *dt;
     int eonly, sub;
+    // with cfl set: the CFL maxima of the leaf children, from the values
+    // the restriction reads, into part (by leaf index, from leaf_of), and
+    // the cells with rho <= 0 or p <= 0, or not finite, into cnt[2], cnt[3]
+    int cfl;
+    double *part;
+    const int32_t *leaf_of;
+    unsigned long long *cnt;
+    double gamma;
 };
 
 struct RefluxArgs {
@@ -73,6 +81,7 @@ struct CflArgs {
     const int32_t *leaves;
     int nleaves;
     double *part;
+    const int32_t *part_idx;  // part index of each listed leaf (null: its list index)
     double *cpart;  // conduction: per leaf max kappa T / p (null: off)
     unsigned long long *cnt;
     double gamma, kappa0;

@@ -46,8 +46,9 @@ struct SimRec {
 
 // byte offsets of the tables inside the caller's workspace
 struct WsLayout {
-    size_t blocks, desc, parent, children, fbidx, leaves, restrict_list, prolong_list,
-        frame_list, reflux_slots, reflux_start, reflux_recs, sims, lvl_dx, dt, cfl_part,
+    size_t blocks, desc, parent, children, fbidx, leaves, leaf_of, orphans, orphan_idx,
+        restrict_list, prolong_list, frame_list, reflux_slots, reflux_start, reflux_recs, sims,
+        lvl_dx, dt, dt2, cfl_part,
         cond_part, tot_part, counters, fbuf, remap, newlist, shadow, total;
 };
 

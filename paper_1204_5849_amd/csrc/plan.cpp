@@ -273,9 +273,18 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
         }
     }
     c->leaves.clear();
+    c->leaf_of.assign(n, -1);
+    c->orphans.clear();
+    c->orphan_idx.clear();
     for (int s = 0; s < n; s++)
-        if (c->blk[s].leaf)
+        if (c->blk[s].leaf) {
+            c->leaf_of[s] = (int32_t)c->leaves.size();
+            if (c->parent[s] < 0) {
+                c->orphans.push_back(s);
+                c->orphan_idx.push_back((int32_t)c->leaves.size());
+            }
             c->leaves.push_back(s);
+        }
     c->nleaves = (int)c->leaves.size();
 
     // ---- per-simulation records: leaf ranges (leaves are grouped by sim),
@@ -468,6 +477,9 @@ void map_plan_layout(map_ctx *c)
     L.children = take(n * 8 * sizeof(int32_t));
     L.fbidx = take(n * 6 * sizeof(int32_t));
     L.leaves = take((size_t)c->nleaves * sizeof(int32_t));
+    L.leaf_of = take(n * sizeof(int32_t));
+    L.orphans = take(c->orphans.size() * sizeof(int32_t));
+    L.orphan_idx = take(c->orphan_idx.size() * sizeof(int32_t));
     L.restrict_list = take(c->restrict_list.size() * sizeof(int32_t));
     L.prolong_list = take(c->prolong_list.size() * sizeof(int32_t));
     L.frame_list = take(c->frame_list.size() * sizeof(int32_t));
@@ -477,6 +489,7 @@ void map_plan_layout(map_ctx *c)
     L.sims = take(ns * sizeof(SimRec));
     L.lvl_dx = take(c->lvl_dx.size() * sizeof(double));
     L.dt = take(ns * sizeof(map_dt));
+    L.dt2 = take(ns * sizeof(map_dt));
     L.cfl_part = take((size_t)c->nleaves * sizeof(double));
     L.cond_part = take((size_t)c->nleaves * sizeof(double));
     L.tot_part = take((size_t)c->nleaves * NV * sizeof(double));

@@ -21,6 +21,9 @@ struct map_ctx {
     std::vector<mapk::Desc> desc;          // [slot][27]
     std::vector<int32_t> fbidx;            // [slot][6], -1 if none
     std::vector<int32_t> leaves;           // leaf slots in Morton order
+    std::vector<int32_t> leaf_of;          // by slot: index in `leaves`, -1 for parents
+    std::vector<int32_t> orphans;          // leaves without a parent (level 1), and
+    std::vector<int32_t> orphan_idx;       // their indices in `leaves`
     std::vector<mapk::SimRec> simrec;
     std::vector<double> lvl_dx;            // [sim][MAXL + 1][3]
     std::vector<int32_t> restrict_list;    // parent slots, grouped by level
@@ -48,10 +51,14 @@ struct map_ctx {
     // block), and the new blocks (host copies kept for the async upload)
     std::vector<int32_t> remap_src, remap_new;
 
-    // captured cycle
-    void *graph_exec = nullptr;  // hipGraphExec_t
+    // captured cycles: the first pair of a run (it forms its first dt
+    // records) and the pairs after it (they start from the records the pair
+    // before formed during its last restriction)
+    void *graph_exec = nullptr;   // hipGraphExec_t
+    void *graph_exec2 = nullptr;  // hipGraphExec_t
     void *graph_U = nullptr;
     void *cap_stream = nullptr;  // hipStream_t used for capture
+    size_t last_dt = 0;          // workspace offset of the last cycle's dt records
 
     size_t face_cells() const { return nd == 3 ? (size_t)mapk::NB * mapk::NB : (size_t)mapk::NB; }
 };
