@@ -230,7 +230,11 @@ map_status map_status_flags(map_ctx *ctx, uint64_t counters[4], void *stream);
  * parents that feed prolongation, prolongation level by level), then the
  * conduction subcycle when params.cond_mode is on (map_conduct), with dt
  * kept on the device (the record of the last step is copied to dt_dev if it
- * is not NULL).  LF and MMC cycles alternate between U and the workspace's
+ * is not NULL).  Without conduction, every cycle after the first of a call
+ * takes its dt from the cycle before: that cycle's restriction also forms
+ * the CFL maxima of the leaves with a parent (their values are final after
+ * reflux), a small pass those of the leaves without one; the records equal
+ * those map_cfl_dt would form from the state at the start of the cycle.  LF and MMC cycles alternate between U and the workspace's
  * shadow state, and an odd nsteps ends with one device copy back into U;
  * WENO cycles update U in place (the shadow holds the stage).  On return U
  * holds the interiors of every block and its prolongated ghosts; the
@@ -240,8 +244,10 @@ map_status map_advance(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *
 
 /* Same cycles and result as map_advance: the pair of cycles U -> shadow ->
  * U (WENO: two in-place cycles) is captured once per U into a HIP graph and
- * replayed nsteps / 2 times on `stream`; an odd nsteps adds one eager cycle
- * (and for LF and MMC the copy back). */
+ * replayed nsteps / 2 times on `stream` (without conduction, two captures:
+ * the first pair of a call forms its first dt, the later ones start from
+ * the dt the pair before formed); an odd nsteps adds one eager cycle (and
+ * for LF and MMC the copy back). */
 map_status map_graph_run(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
 
 /* MAP_LAUNCH_BATCHED: one launch per stage over the joint work list of all
