@@ -63,6 +63,7 @@ map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all, int eonly_sub 
     a.dt = dptr<map_dt>(c, c->ws.dt);
     a.eonly = eonly_sub >= 0;
     a.sub = eonly_sub;
+    a.nsims = (int)c->sims.size();
     a.desc = dptr<Desc>(c, c->ws.desc);
     a.blk = dptr<BlockRec>(c, c->ws.blocks);
     a.parent = dptr<int32_t>(c, c->ws.parent);
@@ -104,6 +105,7 @@ map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1, 
     a.dt = dptr<map_dt>(c, c->ws.dt);
     a.eonly = eonly_sub >= 0;
     a.sub = eonly_sub;
+    a.nsims = (int)c->sims.size();
     a.cfl = cfl;
     a.part = dptr<double>(c, c->ws.cfl_part);
     a.leaf_of = dptr<int32_t>(c, c->ws.leaf_of);
@@ -263,6 +265,7 @@ map_status run_reflux(map_ctx *c, void *U, const map_dt *dt, hipStream_t s, int 
     RefluxArgs a{};
     a.eonly = eonly_sub >= 0;
     a.sub = eonly_sub;
+    a.nsims = (int)c->sims.size();
     a.U = U;
     a.slots = dptr<int32_t>(c, c->ws.reflux_slots);
     a.start = dptr<int32_t>(c, c->ws.reflux_start);
@@ -305,6 +308,7 @@ map_status run_conduct(map_ctx *c, void *U, void *scratch, const map_dt *dt, hip
     a.mode = c->p.cond_mode;
     a.list = dptr<int32_t>(c, c->ws.leaves);
     a.nitems = c->nleaves;
+    a.nsims = (int)c->sims.size();
     for (int i = 0; i < c->p.cond_max_sub; i++) {
         a.sub = i;
         HIPCHK(launch_conduct(c->nd, fp64(c), a, s));

@@ -91,6 +91,8 @@ __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
     constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC, BPW = FG<NDIM>::BPW;
     constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     T *U = (T *)a.U;
+    if (EO && sub_idle(a.dt, a.nsims, a.sub))
+        return;
     int first, stride, end;
     xcd_range(a.nitems, first, stride, end);
     for (int item = first; item < end; item += stride) {
@@ -160,6 +162,8 @@ __global__ void __launch_bounds__(NTA) k_prolong_ghosts(FillArgs a)
     constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC;
     constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     T *U = (T *)a.U;
+    if (EO && sub_idle(a.dt, a.nsims, a.sub))
+        return;
     int first, stride, end;
     xcd_range(a.nitems, first, stride, end);  // siblings share the parent tile in L2
     for (int item = first; item < end; item += stride) {
@@ -278,6 +282,8 @@ __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
     static_assert(!CFL || (!EO && NTA == NB * NB), "CFL: all variables, one column per thread");
     __shared__ unsigned long long smax[CFL ? NCH : 1];
     T *U = (T *)a.U;
+    if (EO && sub_idle(a.dt, a.nsims, a.sub))
+        return;
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         const int slot = a.list[item];
         if (EO && sub_inactive(a.dt, a.blk[slot].sim, a.sub))
@@ -383,6 +389,8 @@ __global__ void __launch_bounds__(NTA) k_reflux(RefluxArgs a)
     constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     T *U = (T *)a.U;
     const T *fb = (const T *)a.fbuf;
+    if (EO && sub_idle(a.dt, a.nsims, a.sub))
+        return;
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         const int slot = a.slots[item];
         const BlockRec br = a.blk[slot];
@@ -732,7 +740,9 @@ hipError_t launch_fill_copy(int ndim, bool fp64, const FillArgs &a, int grid, hi
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
+    int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
+    if (a.eonly && g > SUB_GRID)
+        g = SUB_GRID;
     DISPATCH_EO(ndim, fp64, a.eonly, k_fill_copy, dim3(g), dim3(NTA), 0, s, a);
     return hipGetLastError();
 }
@@ -741,7 +751,8 @@ hipError_t launch_prolong_ghosts(int ndim, bool fp64, const FillArgs &a, hipStre
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    DISPATCH_EO(ndim, fp64, a.eonly, k_prolong_ghosts, dim3(a.nitems), dim3(NTA), 0, s, a);
+    const int g = a.eonly && a.nitems > SUB_GRID ? SUB_GRID : a.nitems;
+    DISPATCH_EO(ndim, fp64, a.eonly, k_prolong_ghosts, dim3(g), dim3(NTA), 0, s, a);
     return hipGetLastError();
 }
 
@@ -762,7 +773,8 @@ hipError_t launch_restrict(int ndim, bool fp64, const RestrictArgs &a, hipStream
             return hipErrorInvalidValue;
         DISPATCH_CFL(ndim, fp64, dim3(a.nitems), dim3(NTA), 0, s, a);
     } else {
-        DISPATCH_EO(ndim, fp64, a.eonly, k_restrict, dim3(a.nitems), dim3(NTA), 0, s, a);
+        const int g = a.eonly && a.nitems > SUB_GRID ? SUB_GRID : a.nitems;
+        DISPATCH_EO(ndim, fp64, a.eonly, k_restrict, dim3(g), dim3(NTA), 0, s, a);
     }
     return hipGetLastError();
 }
@@ -771,7 +783,8 @@ hipError_t launch_reflux(int ndim, bool fp64, const RefluxArgs &a, hipStream_t s
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    DISPATCH_EO(ndim, fp64, a.eonly, k_reflux, dim3(a.nitems), dim3(NTA), 0, s, a);
+    const int g = a.eonly && a.nitems > SUB_GRID ? SUB_GRID : a.nitems;
+    DISPATCH_EO(ndim, fp64, a.eonly, k_reflux, dim3(g), dim3(NTA), 0, s, a);
     return hipGetLastError();
 }
 

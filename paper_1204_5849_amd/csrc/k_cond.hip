@@ -158,6 +158,8 @@ __global__ void __launch_bounds__(NTK) k_conduct(CondArgs a)
     const bool g2 = t + NTK < RP;
     const int gx0 = t % RW - 1, gy0 = t / RW - 1;
     const int gx1 = (t + NTK) % RW - 1, gy1 = (t + NTK) / RW - 1;
+    if (sub_idle(a.dt, a.nsims, a.sub))
+        return;
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         const int slot = a.list[item];
         const BlockRec br = a.blk[slot];
@@ -310,6 +312,8 @@ __global__ void __launch_bounds__(NTC) k_cond_commit(CondArgs a)
     constexpr int NI = NDIM == 3 ? NB * NB * NB : NB * NB;
     T *U = (T *)a.U;
     const T *S = (const T *)a.S;
+    if (sub_idle(a.dt, a.nsims, a.sub))
+        return;
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         const int slot = a.list[item];
         if (a.sub >= a.dt[a.blk[slot].sim].nsub)
@@ -338,6 +342,11 @@ __global__ void __launch_bounds__(NTC) k_cond_commit(CondArgs a)
         }                                                                  \
     } while (0)
 
+// (k_conduct keeps one workgroup per leaf: its occupancy is set by LDS, and
+// a persistent grid of SUB_GRID workgroups ended on a partial round and ran
+// 9 % slower; an idle one returns after one read)
+static int sub_grid(const CondArgs &a) { return a.nitems > SUB_GRID ? SUB_GRID : a.nitems; }
+
 template <int NDIM, typename T>
 static void launch_conduct_t(const CondArgs &a, hipStream_t s)
 {
@@ -362,7 +371,7 @@ hipError_t launch_cond_commit(int ndim, bool fp64, const CondArgs &a, hipStream_
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    COND_DISPATCH(ndim, fp64, k_cond_commit, dim3(a.nitems), dim3(NTC), 0, s, a);
+    COND_DISPATCH(ndim, fp64, k_cond_commit, dim3(sub_grid(a)), dim3(NTC), 0, s, a);
     return hipGetLastError();
 }
 

@@ -42,7 +42,7 @@ struct FillArgs {
     const int32_t *copy_list;  // copies: slots (null: slot = index)
     int slot_base, slot_end, nitems;  // copies: index range [slot_base, slot_end)
     const map_dt *dt;
-    int eonly, sub;
+    int eonly, sub, nsims;
 };
 
 struct RestrictArgs {
@@ -52,7 +52,7 @@ struct RestrictArgs {
     int nitems;
     const BlockRec *blk;
     const map_dt *dt;
-    int eonly, sub;
+    int eonly, sub, nsims;
     // with cfl set: the CFL maxima of the leaf children, from the values
     // the restriction reads, into part (by leaf index, from leaf_of), and
     // the cells with rho <= 0 or p <= 0, or not finite, into cnt[2], cnt[3]
@@ -73,7 +73,7 @@ struct RefluxArgs {
     const double *lvl_dx;
     const void *fbuf;
     int nitems;
-    int eonly, sub;  // conduction sub-step: energy only, dt_sub
+    int eonly, sub, nsims;  // conduction sub-step: energy only, dt_sub
 };
 
 struct CflArgs {
@@ -111,8 +111,24 @@ struct CondArgs {
     const int32_t *fbidx;
     void *fbuf;
     double gamma, kappa0;
-    int khalf, mode, sub;
+    int khalf, mode, sub, nsims;
 };
+
+// a conduction sub-step beyond the subcycle of every simulation: the
+// sub-step's kernels return at once (they are launched whatever nsub is, so
+// that the launch sequence does not depend on data)
+__device__ __forceinline__ bool sub_idle(const map_dt *dt, int nsims, int sub)
+{
+    for (int s = 0; s < nsims; s++)
+        if (sub < dt[s].nsub)
+            return false;
+    return true;
+}
+
+// grid of a conduction sub-step launch: a persistent grid of at most this
+// many workgroups, so that an idle sub-step costs a few thousand tiny
+// workgroups rather than one per block
+constexpr int SUB_GRID = 2048;
 
 struct TotalsArgs {
     const void *U;
