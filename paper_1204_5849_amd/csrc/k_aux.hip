@@ -217,9 +217,9 @@ __global__ void __launch_bounds__(NTA) k_prolong_blocks(FillArgs a)
 }
 
 // ---- restriction: parent interior = mean of the 2^d child cells it covers
-// (Sec. 4.2, Sec. 4.3 step 1); one workgroup per parent.  The two cells of
-// an x pair are adjacent and 2-element aligned in the padded tile, so each
-// pair is one vector load; the sum is taken x pairs first, then y, then z.
+// (Sec. 4.2, Sec. 4.3 step 1).  The two cells of an x pair are adjacent and
+// 2-element aligned in the padded tile, so each pair is one vector load; the
+// sum is taken x pairs first, then y, then z.
 template <typename T>
 struct Pair;
 template <>
@@ -263,15 +263,14 @@ __device__ __forceinline__ double cfl_speed(const double (&u)[NV], double gamma,
     return s;
 }
 
-// ---- restriction: one workgroup per parent, one parent cell per thread and
-//      pass; with CFL, the CFL maxima of the leaf children as well (the
-//      values the restriction reads are the leaves' final ones after
-//      reflux), so that the next cycle's dt needs no pass of its own over
-//      those leaves: a thread's parent cells lie in one child per half of the
-//      parent in z, each thread keeps its maxima per half, and the
-//      workgroup combines them per child with LDS atomics on the bit
-//      patterns (the speeds are finite and non-negative, so those order like
-//      the values)
+// The restriction kernel: one workgroup per parent, one parent cell per
+// thread and pass.  With CFL it also forms the CFL maxima of the leaf
+// children (the values it reads are the leaves' final ones after reflux),
+// so that the next cycle's dt needs no pass of its own over those leaves: a
+// thread's parent cells lie in one child per half of the parent in z, each
+// thread keeps its maxima per half, and the workgroup combines them per
+// child with LDS atomics on the bit patterns (the speeds are finite and
+// non-negative, so those order like the values).
 template <int NDIM, typename T, bool EO, bool CFL = false>
 __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
 {
