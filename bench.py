@@ -245,6 +245,33 @@ def time_regrid(sim, wl):
     return out
 
 
+def time_fp64_batched(name, steps, autotune=True):
+    """The LF cycle with an FP64 state on the same workload: batched
+    persistent launches captured in a HIP graph, as the FP32 headline run."""
+    import torch
+    from paper_1204_5849_amd.sim import Simulation
+    wl64 = build_workload(name, "fp64")
+    sim = Simulation(wl64, precision="fp64")
+    sim.load_initial()
+    chosen = sim.autotune() if autotune else None
+    sim.graph_run(2)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.graph_run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    st, cnt = sim.flags()
+    t_step = time_step_kernel(sim, 5)
+    out = {"ms_per_step": el / steps * 1e3, "value": wl64.n_leaf_cells() * steps / el,
+           "unit": "cell-updates/s", "steps": steps, "step_kernel_ms": t_step * 1e3,
+           "grids": chosen, "flags": [int(c) for c in cnt],
+           "note": "FP64 state and arithmetic, hipGraph, batched persistent"}
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_weno(wl, precision, steps, autotune=True, riemann="rusanov"):
     """Whole WENO cycles (two stages, the boundary procedure on the stage,
     reflux, restriction, fill) on the same blocks and initial data, captured
@@ -470,6 +497,14 @@ def main():
         r = result["conduction"]
         log(f"conduction: {r['ms_per_step']:.3f} ms/step with {r['nsub_last_step']} sub-steps, "
             f"{r['subcycle_ms_per_substep']:.3f} ms per sub-step")
+
+    if not args.no_plain and args.precision == "fp32":
+        log("FP64 batched path on the same workload")
+        result["fp64_batched"] = time_fp64_batched(args.workload, args.weno_steps,
+                                                   not args.no_autotune)
+        r = result["fp64_batched"]
+        log(f"fp64 batched: {r['ms_per_step']:.3f} ms/step, {r['value'] / 1e9:.3f} G "
+            f"cell-updates/s, step kernel {r['step_kernel_ms']:.3f} ms")
 
     if not args.no_plain:
         log("FP64 plain per-block path on the same workload")

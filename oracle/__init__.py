@@ -420,7 +420,8 @@ class Amr:
         self.leaf = np.array([bool(lib().orc_amr_is_leaf(self.h, b)) for b in range(len(self.keys))])
 
     def __del__(self):
-        if getattr(self, "h", None):
+        # (at interpreter exit the module's globals may already be gone)
+        if getattr(self, "h", None) and callable(lib):
             lib().orc_amr_free(self.h)
             self.h = None
 

@@ -57,12 +57,15 @@ class Simulation:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
+        # at interpreter exit the binding's module globals may already be
+        # gone; the process releases the context then
+        destroy = getattr(N, "map_destroy", None) if N is not None else None
+        if ctx and destroy is not None:
             try:
                 torch.cuda.synchronize(self.device)
             except Exception:
                 pass
-            N.map_destroy(ctx)
+            destroy(ctx)
             self.ctx = None
 
     # ---------------------------------------------------------------- data
