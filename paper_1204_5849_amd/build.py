@@ -12,8 +12,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmap.so")
-SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step2.hip", "k_step3.hip", "k_step_mmc.hip",
-           "k_aux.hip", "k_regrid.hip", "k_cond.hip"]
+SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step2.hip", "k_step3.hip", "k_step3_lf.hip",
+           "k_step_mmc.hip", "k_aux.hip", "k_regrid.hip", "k_cond.hip"]
+# per-source options: the FP32 3-D LF update is VALU-bound at the
+# 256-register limit, and LLVM's ILP-first scheduler ran it 3 % faster on
+# MI355X; the WENO stages and the FP64 LF update (k_step3.hip) ran 3 % and
+# 6 % slower with it and keep the default
+EXTRA = {"k_step3_lf.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 ARCH = os.environ.get("MAP_OFFLOAD_ARCH", "gfx950")
 
 
@@ -37,7 +42,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".", "_") + ".o")
         objs.append(obj)
-        cmd = [hipcc(), *common, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), *common, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
             cmd = [hipcc(), *[a for a in common if not a.startswith("--offload")],
                    "-x", "c++", "-c", os.path.join(CSRC, src), "-o", obj]

@@ -221,17 +221,18 @@ def test_graph_equals_eager_and_per_block_equals_batched(dev):
     assert np.array_equal(a2, b.state_by_key())
 
 
-@pytest.mark.parametrize("ndim,scheme", [(2, "lf"), (3, "lf"), (3, "weno")])
-def test_cycles_in_one_call_equal_cycle_by_cycle(dev, ndim, scheme):
+@pytest.mark.parametrize("ndim,scheme,precision", [(2, "lf", "fp64"), (3, "lf", "fp64"),
+                                                    (3, "weno", "fp64"), (3, "lf", "fp32")])
+def test_cycles_in_one_call_equal_cycle_by_cycle(dev, ndim, scheme, precision):
     """n cycles in one call (alternating U and the shadow, or in place for
     WENO; eager or as replays of the captured pair) leave the state and the
     last cycle's dt records of n calls of one cycle, bit for bit, for odd and
     even counts and repeated calls."""
     import dataclasses
-    _say(f"n cycles per call vs one per call ndim={ndim} {scheme}")
+    _say(f"n cycles per call vs one per call ndim={ndim} {scheme} {precision}")
     sims, keys = _tree(ndim, 7 + ndim, "mixed")
     w = W.Workload(name="tree", ndim=ndim, sims=sims, keys=keys, ic=_tree_ic)
-    w = dataclasses.replace(w, scheme=scheme)
+    w = dataclasses.replace(w, scheme=scheme, precision=precision)
     ref, a, b = _sim(w), _sim(w), _sim(w)
     for n in (5, 4, 1, 2):
         for _ in range(n):
