@@ -107,7 +107,7 @@ ALU_PEAK_TFLOPS = 78.6
 def step_sources_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_step2.hip", "k_step3.hpp", "k_step3_lf.hip", "k_step3.hip", "step_common.hpp",
+    for f in ("k_step2.hip", "k_step3.hpp", "k_step3_ilp.hip", "k_step3.hip", "step_common.hpp",
               "tile.hpp", "physics.hpp", "kernels.hpp", "map_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1204_5849_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())

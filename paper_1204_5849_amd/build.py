@@ -12,13 +12,15 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmap.so")
-SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step2.hip", "k_step3.hip", "k_step3_lf.hip",
+SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step2.hip", "k_step3.hip", "k_step3_ilp.hip",
            "k_step_mmc.hip", "k_aux.hip", "k_regrid.hip", "k_cond.hip"]
-# per-source options: the FP32 3-D LF update is VALU-bound at the
-# 256-register limit, and LLVM's ILP-first scheduler ran it 3 % faster on
-# MI355X; the WENO stages and the FP64 LF update (k_step3.hip) ran 3 % and
-# 6 % slower with it and keep the default
-EXTRA = {"k_step3_lf.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+# per-source options: LLVM's ILP-first scheduler, measured per kernel on
+# MI355X (Harris 128^3, FP32): the FP32 3-D LF update (VALU-bound at the
+# 256-register limit) 3 % faster, the first WENO stage 5 % and the
+# conduction sub-step 3 % faster; the second WENO stage (10 %) and the FP64
+# LF update (6 %) slower, so those stay in k_step3.hip with the default
+EXTRA = {"k_step3_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+         "k_cond.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 ARCH = os.environ.get("MAP_OFFLOAD_ARCH", "gfx950")
 
 

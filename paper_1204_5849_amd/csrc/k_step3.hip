@@ -1,5 +1,6 @@
-// k_step3.hip -- launches of the 3-D block update: the WENO stages and the
-// FP64 LF step are instantiated here, the FP32 LF step in k_step3_lf.hip.
+// k_step3.hip -- launches of the 3-D block update: the FP64 instances and
+// the second FP32 WENO stage are instantiated here, the FP32 LF step and
+// first WENO stage in k_step3_ilp.hip.
 #include "k_step3.hpp"
 
 namespace mapk {
@@ -30,17 +31,26 @@ static hipError_t launch3_rs(int sch, const StepArgs &a, int grid, hipStream_t s
             return a.riemann == MAP_HLLC ? launch3_lf64<T, RESIST, MAP_HLLC>(a, grid, s)
                                          : launch3_lf64<T, RESIST, MAP_RUSANOV>(a, grid, s);
     }
-    if (a.riemann == MAP_HLLC)
-        return launch3_weno<T, MIXED, RESIST, MAP_HLLC>(sch, a, grid, s);
-    return launch3_weno<T, MIXED, RESIST, MAP_RUSANOV>(sch, a, grid, s);
+    if constexpr (MIXED) {
+        // FP32: only the second WENO stage is instantiated here (each
+        // instance lives in one translation unit, so the scheduler it was
+        // compiled with is the one that runs)
+        if (a.riemann == MAP_HLLC)
+            return launch3<T, MIXED, RESIST, SCH_WENO2, MAP_MINMOD, MAP_HLLC>(a, grid, s);
+        return launch3<T, MIXED, RESIST, SCH_WENO2, MAP_MINMOD, MAP_RUSANOV>(a, grid, s);
+    } else {
+        if (a.riemann == MAP_HLLC)
+            return launch3_weno<T, MIXED, RESIST, MAP_HLLC>(sch, a, grid, s);
+        return launch3_weno<T, MIXED, RESIST, MAP_RUSANOV>(sch, a, grid, s);
+    }
 }
 
 hipError_t launch_step3(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s)
 {
     if (a.nitems <= 0)
         return hipSuccess;
-    if (sch == SCH_LF && !fp64)
-        return launch_step3_lf32(resist, a, grid, s);
+    if (!fp64 && sch != SCH_WENO2)
+        return launch_step3_ilp(sch, resist, a, grid, s);
     if (fp64)
         return resist ? launch3_rs<double, false, true>(sch, a, grid, s)
                       : launch3_rs<double, false, false>(sch, a, grid, s);
