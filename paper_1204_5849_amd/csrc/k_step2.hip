@@ -2,7 +2,7 @@
 // (paper Sec. 3.2) or one stage of WENO with TVD Runge-Kutta 2 (Sec. 3.3),
 // both directions together (Sec. 3.7), with the EGLM source terms (Sec. 2),
 // uniform resistivity (Sec. 3.5) and exact psi damping (the 3-D kernel is in
-// k_step3.hip).
+// k_step3.hpp).
 //
 // Layout and schedule (gfx950): a workgroup of 256 threads holds 14 blocks,
 // 18 columns each (x = -1 .. 16: the interior and the cell on each side
