@@ -15,10 +15,11 @@ LIB = os.path.join(PKG, "libmap.so")
 SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step2.hip", "k_step3.hip", "k_step3_ilp.hip",
            "k_step_mmc.hip", "k_aux.hip", "k_regrid.hip", "k_cond.hip"]
 # per-source options: LLVM's ILP-first scheduler, measured per kernel on
-# MI355X (Harris 128^3, FP32): the FP32 3-D LF update (VALU-bound at the
-# 256-register limit) 3 % faster, the first WENO stage 5 % and the
-# conduction sub-step 3 % faster; the second WENO stage (10 %) and the FP64
-# LF update (6 %) slower, so those stay in k_step3.hip with the default
+# MI355X (FP32): the resistive 3-D LF update (VALU-bound at the 256-register
+# limit) 3 % faster with Rusanov and 6 % with HLLC, the resistive first WENO
+# stage 5 % and the conduction sub-step 3 % faster; the non-resistive LF
+# update (2-3 %), the second WENO stage (10 %) and the FP64 LF update (6 %)
+# slower, so those stay in k_step3.hip with the default
 EXTRA = {"k_step3_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
          "k_cond.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 ARCH = os.environ.get("MAP_OFFLOAD_ARCH", "gfx950")

@@ -31,8 +31,8 @@
 //     stores u1 without damping, stage 2 stores (u + u1 + dt L(u1)) / 2, u
 //     read from U_base at the cell itself, then damps psi, and the reflux
 //     face fluxes become the mean of both stages' fluxes.
-// A persistent grid strides over the leaf list.  The FP32 LF and first WENO
-// stage instances are compiled in k_step3_ilp.hip, the others in
+// A persistent grid strides over the leaf list.  The FP32 resistive LF and
+// first WENO stage instances are compiled in k_step3_ilp.hip, the others in
 // k_step3.hip: they take different instruction schedulers (see the build
 // script).
 #pragma once

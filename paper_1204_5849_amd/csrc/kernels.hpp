@@ -162,7 +162,7 @@ struct RemapArgs {
 // launchers (defined in the .hip files); return hipError_t of the launch
 hipError_t launch_step2(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s);
 hipError_t launch_step3(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s);
-hipError_t launch_step3_ilp(int sch, bool resist, const StepArgs &a, int grid, hipStream_t s);
+hipError_t launch_step3_ilp(int sch, const StepArgs &a, int grid, hipStream_t s);
 hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double alpha_unused, int grid,
                            hipStream_t s);
 int step_blocks_per_group(int ndim, int scheme);
