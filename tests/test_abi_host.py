@@ -174,3 +174,23 @@ def test_neighbours_match_brute_force(ndim, bc):
                         src.append(G // n)
                     want = index.get((s, lv, *src), -1)
                     assert got[i, di] == want, (i, (dx, dy, dz))
+
+
+def test_each_step_instance_is_compiled_once():
+    """The 3-D step kernel template is instantiated from two translation units
+    compiled with different instruction schedulers; an instance defined in
+    both would leave the linker to pick one of the two copies, so the sets of
+    instances must be disjoint (and together hold all 40)."""
+    import shutil
+    import subprocess
+    from paper_1204_5849_amd import build as B
+    objs = [os.path.join(B.PKG, "_build", f) for f in ("k_step3_hip.o", "k_step3_ilp_hip.o")]
+    if not all(os.path.exists(o) for o in objs) or not shutil.which("nm"):
+        pytest.skip("step objects not built here")
+    sets = []
+    for o in objs:
+        out = subprocess.run(["nm", "-C", o], capture_output=True, text=True, check=True).stdout
+        sets.append(set(re.findall(r"k_step3<([^>]*)>", out)))
+    assert not (sets[0] & sets[1]), sorted(sets[0] & sets[1])
+    # 2 precisions x 2 (resistivity) x (3 LF limiters + 2 WENO stages) x 2 fluxes
+    assert len(sets[0] | sets[1]) == 40
