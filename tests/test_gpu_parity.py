@@ -250,6 +250,41 @@ def test_cycles_in_one_call_equal_cycle_by_cycle(dev, ndim, scheme, precision):
             assert np.array_equal(x.state_by_key(), ru), n
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_chained_dt_two_simulations(dev, orc, ndim):
+    """Two simulations of different sizes and edges, each a random 2:1 tree
+    with parents and leaves without one: the dt records of each, formed in a
+    cycle's restriction and the pass over the leaves without a parent, equal
+    those of one cycle per call bit for bit, and the state matches the
+    oracle."""
+    _say(f"chained dt, two simulations, ndim={ndim}")
+    # seeds for which both simulations have parents and level-1 leaves
+    rng = np.random.default_rng(42 if ndim == 2 else 39)
+    nb = ((3, 2, 1), (2, 2, 1)) if ndim == 2 else ((3, 2, 2), (2, 2, 3))
+    per = (("periodic", "periodic"),) * 3
+    mixed = (("periodic", "periodic"), ("outflow", "outflow"), ("periodic", "periodic"))
+    sims = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb[0], bc=per),
+            W.SimDesc(lo=(0, 0, 0), hi=(2, 1, 2), nbase=nb[1], bc=mixed)]
+    keys = random_tree(sims, ndim, 3, 0.35 if ndim == 2 else 0.15, rng)
+    w = W.Workload(name="tree2", ndim=ndim, sims=sims, keys=keys, ic=_tree_ic)
+    leaves = W.leaf_mask(keys)
+    for sim in (0, 1):
+        mine = keys[:, 0] == sim
+        assert (mine & (keys[:, 1] > 1)).any() and (mine & (keys[:, 1] == 1) & leaves).any()
+    ref, a = _sim(w), _sim(w)
+    for _ in range(4):
+        ref.advance(1)
+    a.advance(4)
+    A = orc.load_workload(w)
+    A.run(4)
+    for x in (ref, a):
+        x.fill()
+        x.sync()
+    assert np.array_equal(a.dt.cpu().numpy(), ref.dt.cpu().numpy())
+    assert np.array_equal(a.state_by_key(), ref.state_by_key())
+    _check(w, a.state_by_key(), A.state, TOL64, f"two simulations ndim={ndim}")
+
+
 def test_determinism_3d(dev):
     _say("determinism blast small fp32")
     w = W.blast3d(nbase=2, levels=2, precision="fp32")
