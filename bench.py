@@ -114,6 +114,23 @@ def step_sources_hash():
     return h.hexdigest()[:16]
 
 
+def measured_valu_busy(workload_name):
+    """VALU busy fraction of the step kernel from the committed SQ-counter
+    summary, if it was taken on the current step-kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{workload_name}_fp32_step_sq_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("step_valu:"):
+            for kv in line.split()[1:]:
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("sources") != step_sources_hash() or "busy" not in vals:
+        return None
+    return float(vals["busy"])
+
+
 def measured_traffic(workload_name):
     """HBM bytes per step launch from the committed counter summary, if it was
     taken on the current step-kernel sources (else None)."""
@@ -432,6 +449,7 @@ def main():
     fpc = FLOPS_PER_CELL[(wl.ndim, wl.eta > 0)]
     tflops = nleaf_cells * fpc / t_step / 1e12
     traffic = measured_traffic(wl.name) if args.precision == "fp32" else None
+    valu_busy = measured_valu_busy(wl.name) if args.precision == "fp32" else None
     log(f"step kernel {t_step * 1e3:.3f} ms/launch, {achieved:.1f} GB/s algorithmic, "
         f"{tflops:.2f} TFLOP/s")
 
@@ -456,6 +474,7 @@ def main():
                    else "hipGraph, batched persistent", "grids": chosen},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
+                     "valu_busy": valu_busy,
                      "kernel": "k_step3 (LF)" if wl.ndim == 3 else "k_step2 (LF)",
                      "kernel_ms": t_step * 1e3,
                      "flops_per_cell_update": fpc, "algorithmic_bytes_per_launch": bytes_step,
