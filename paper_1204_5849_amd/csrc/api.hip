@@ -116,7 +116,9 @@ map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1, 
         if (hi <= lo)
             continue;
         a.list = dptr<int32_t>(c, c->ws.restrict_list) + lo;
-        a.nitems = hi - lo;
+        // a level with fewer parents than CUs takes one workgroup per child
+        a.per_child = hi - lo < c->ncu;
+        a.nitems = (hi - lo) * (a.per_child ? (c->nd == 3 ? 8 : 4) : 1);
         HIPCHK(launch_restrict(c->nd, fp64(c), a, s));
     }
     return MAP_OK;
@@ -523,6 +525,11 @@ map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
     // the host vectors above are pageable: finish the copies before returning
     HIPCHK(hipStreamSynchronize(s));
     c->last_dt = c->ws.dt;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        ncu > 0)
+        c->ncu = ncu;
     c->bound = true;
     return MAP_OK;
 }

@@ -264,7 +264,9 @@ __device__ __forceinline__ double cfl_speed(const double (&u)[NV], double gamma,
 }
 
 // The restriction kernel: one workgroup per parent, one parent cell per
-// thread and pass.  With CFL it also forms the CFL maxima of the leaf
+// thread and pass, or, for a level with fewer parents than CUs, one
+// workgroup per child (the parent's octant it covers; the same sums).  With
+// CFL it also forms the CFL maxima of the leaf
 // children (the values it reads are the leaves' final ones after reflux),
 // so that the next cycle's dt needs no pass of its own over those leaves: a
 // thread's parent cells lie in one child per half of the parent in z, each
@@ -278,11 +280,121 @@ __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
     constexpr int P = FG<NDIM>::P, NI = FG<NDIM>::NI;
     constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     constexpr int NCH = NDIM == 3 ? 8 : 4, NC = NDIM == 3 ? 8 : 4;
+    constexpr int H = NB / 2, NO = NDIM == 3 ? H * H * H : H * H;  // parent cells per child
     static_assert(!CFL || (!EO && NTA == NB * NB), "CFL: all variables, one column per thread");
     __shared__ unsigned long long smax[CFL ? NCH : 1];
+    __shared__ double red[CFL ? NTA / 64 : 1];
     T *U = (T *)a.U;
     if (EO && sub_idle(a.dt, a.nsims, a.sub))
         return;
+    // parent cell d of ub from the 2^d cells of child tile cu at c0 (its
+    // lowest corner), keeping those cells' values in cv for the CFL speeds
+    auto restrict_cell = [&](T *ub, const T *cu, int c0, int d, T (&cv)[CFL ? NV : 1][CFL ? NC : 1]) {
+#pragma unroll
+        for (int k = K0; k < K1; k++) {
+            const T *q = cu + (size_t)k * P + c0;
+            const V r0 = *reinterpret_cast<const V *>(q);
+            const V r1 = *reinterpret_cast<const V *>(q + PD);
+            T v;
+            if constexpr (NDIM == 2) {
+                v = ((r0.x + r0.y) + (r1.x + r1.y)) * T(0.25);
+            } else {
+                const V r2 = *reinterpret_cast<const V *>(q + PD * PD);
+                const V r3 = *reinterpret_cast<const V *>(q + PD * PD + PD);
+                v = (((r0.x + r0.y) + (r1.x + r1.y)) + ((r2.x + r2.y) + (r3.x + r3.y))) * T(0.125);
+                if constexpr (CFL) {
+                    cv[k][4] = r2.x;
+                    cv[k][5] = r2.y;
+                    cv[k][6] = r3.x;
+                    cv[k][7] = r3.y;
+                }
+            }
+            if constexpr (CFL) {
+                cv[k][0] = r0.x;
+                cv[k][1] = r0.y;
+                cv[k][2] = r1.x;
+                cv[k][3] = r1.y;
+            }
+            ub[(size_t)k * P + d] = v;
+        }
+    };
+    // the CFL speeds of those child cells into the running maximum mh
+    auto cell_speeds = [&](const T (&cv)[CFL ? NV : 1][CFL ? NC : 1], double &mh, unsigned &bad,
+                           unsigned &nonfin) {
+        if constexpr (CFL) {
+#pragma unroll
+            for (int c = 0; c < NC; c++) {
+                double u[NV];
+                bool fin = true;
+#pragma unroll
+                for (int k = 0; k < NV; k++) {
+                    u[k] = (double)cv[k][c];
+                    fin = fin && isfinite(u[k]);
+                }
+                if (!fin) {
+                    nonfin++;
+                    continue;
+                }
+                double pr;
+                bool b;
+                const double sp = cfl_speed<NDIM>(u, a.gamma, pr, b);
+                if (b)
+                    bad++;
+                mh = sp > mh ? sp : mh;
+            }
+        }
+    };
+    auto count = [&](unsigned bad, unsigned nonfin) {
+        if (bad)
+            atomicAdd(&a.cnt[2], (unsigned long long)bad);
+        if (nonfin)
+            atomicAdd(&a.cnt[3], (unsigned long long)nonfin);
+    };
+    if (a.per_child) {
+        // one workgroup per child: the parent's octant (quadrant) it covers
+        for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+            const int slot = a.list[item / NCH];
+            const int cbit = item % NCH;
+            if (EO && sub_inactive(a.dt, a.blk[slot].sim, a.sub))
+                continue;
+            T *ub = U + (size_t)slot * NV * P;
+            const int child = a.children[(size_t)slot * 8 + cbit];
+            const T *cu = U + (size_t)child * NV * P;
+            const int ox = (cbit & 1) * H, oy = ((cbit >> 1) & 1) * H,
+                      oz = NDIM == 3 ? ((cbit >> 2) & 1) * H : 0;
+            const bool leafc = CFL && a.leaf_of[child] >= 0;
+            double m = 0.0;
+            unsigned bad = 0, nonfin = 0;
+            for (int i = threadIdx.x; i < NO; i += NTA) {
+                const int x = i % H, y = (i / H) % H, z = NDIM == 3 ? i / (H * H) : 0;
+                T cv[CFL ? NV : 1][CFL ? NC : 1];
+                restrict_cell(ub, cu, lin<NDIM>(2 * x, 2 * y, 2 * z), lin<NDIM>(ox + x, oy + y, oz + z),
+                              cv);
+                if (leafc)
+                    cell_speeds(cv, m, bad, nonfin);
+            }
+            if constexpr (CFL) {
+                count(bad, nonfin);
+                // wave64 shuffle max, then across the waves through LDS
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double o = __shfl_xor(m, off, 64);
+                    m = o > m ? o : m;
+                }
+                if ((threadIdx.x & 63) == 0)
+                    red[threadIdx.x >> 6] = m;
+                __syncthreads();
+                if (threadIdx.x == 0 && leafc) {
+                    double r = red[0];
+                    for (int w = 1; w < NTA / 64; w++)
+                        r = red[w] > r ? red[w] : r;
+                    a.part[a.leaf_of[child]] = r;
+                }
+                __syncthreads();
+            }
+        }
+        return;
+    }
     for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
         const int slot = a.list[item];
         if (EO && sub_inactive(a.dt, a.blk[slot].sim, a.sub))
@@ -302,61 +414,10 @@ __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
             const int child = a.children[(size_t)slot * 8 + cbit];
             const T *cu = U + (size_t)child * NV * P;
             const int lx = fx % NB, ly = fy % NB, lz = NDIM == 3 ? fz % NB : 0;
-            const int c0 = lin<NDIM>(lx, ly, lz);
-            T cv[CFL ? NV : 1][CFL ? NC : 1];  // the child cells, for the CFL speeds
-#pragma unroll
-            for (int k = K0; k < K1; k++) {
-                const T *q = cu + (size_t)k * P + c0;
-                const V r0 = *reinterpret_cast<const V *>(q);
-                const V r1 = *reinterpret_cast<const V *>(q + PD);
-                T v;
-                if constexpr (NDIM == 2) {
-                    v = ((r0.x + r0.y) + (r1.x + r1.y)) * T(0.25);
-                } else {
-                    const V r2 = *reinterpret_cast<const V *>(q + PD * PD);
-                    const V r3 = *reinterpret_cast<const V *>(q + PD * PD + PD);
-                    v = (((r0.x + r0.y) + (r1.x + r1.y)) + ((r2.x + r2.y) + (r3.x + r3.y))) *
-                        T(0.125);
-                    if constexpr (CFL) {
-                        cv[k][4] = r2.x;
-                        cv[k][5] = r2.y;
-                        cv[k][6] = r3.x;
-                        cv[k][7] = r3.y;
-                    }
-                }
-                if constexpr (CFL) {
-                    cv[k][0] = r0.x;
-                    cv[k][1] = r0.y;
-                    cv[k][2] = r1.x;
-                    cv[k][3] = r1.y;
-                }
-                ub[(size_t)k * P + lin<NDIM>(X, Y, Z)] = v;
-            }
-            if constexpr (CFL) {
-                if (a.leaf_of[child] >= 0) {
-                    double &mh = m[NDIM == 3 ? fz / NB : 0];
-#pragma unroll
-                    for (int c = 0; c < NC; c++) {
-                        double u[NV];
-                        bool fin = true;
-#pragma unroll
-                        for (int k = 0; k < NV; k++) {
-                            u[k] = (double)cv[k][c];
-                            fin = fin && isfinite(u[k]);
-                        }
-                        if (!fin) {
-                            nonfin++;
-                            continue;
-                        }
-                        double pr;
-                        bool b;
-                        const double sp = cfl_speed<NDIM>(u, a.gamma, pr, b);
-                        if (b)
-                            bad++;
-                        mh = sp > mh ? sp : mh;
-                    }
-                }
-            }
+            T cv[CFL ? NV : 1][CFL ? NC : 1];
+            restrict_cell(ub, cu, lin<NDIM>(lx, ly, lz), lin<NDIM>(X, Y, Z), cv);
+            if (CFL && a.leaf_of[child] >= 0)
+                cell_speeds(cv, m[NDIM == 3 ? fz / NB : 0], bad, nonfin);
         }
         if constexpr (CFL) {
             // this thread's children: the one of its column below the middle
@@ -365,10 +426,7 @@ __global__ void __launch_bounds__(NTA) k_restrict(RestrictArgs a)
             atomicMax(&smax[cb], (unsigned long long)__double_as_longlong(m[0]));
             if constexpr (NDIM == 3)
                 atomicMax(&smax[cb | 4], (unsigned long long)__double_as_longlong(m[1]));
-            if (bad)
-                atomicAdd(&a.cnt[2], (unsigned long long)bad);
-            if (nonfin)
-                atomicAdd(&a.cnt[3], (unsigned long long)nonfin);
+            count(bad, nonfin);
             __syncthreads();
             if (threadIdx.x < NCH) {
                 const int li = a.leaf_of[a.children[(size_t)slot * 8 + threadIdx.x]];

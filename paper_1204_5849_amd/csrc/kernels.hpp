@@ -57,6 +57,7 @@ struct RestrictArgs {
     // the restriction reads, into part (by leaf index, from leaf_of), and
     // the cells with rho <= 0 or p <= 0, or not finite, into cnt[2], cnt[3]
     int cfl;
+    int per_child;  // items are parents x 2^d, one child each (else one parent each)
     double *part;
     const int32_t *leaf_of;
     unsigned long long *cnt;

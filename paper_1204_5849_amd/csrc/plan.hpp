@@ -46,6 +46,7 @@ struct map_ctx {
     // launch configuration
     int launch_mode = MAP_LAUNCH_BATCHED;
     int grid_step = 0, grid_fill = 0;
+    int ncu = 256;  // compute units of the bound device
 
     // map_remap: by slot, the source slot in the previous tree (-1: new
     // block), and the new blocks (host copies kept for the async upload)
