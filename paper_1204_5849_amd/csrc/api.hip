@@ -56,11 +56,12 @@ bool fp64(const map_ctx *c) { return c->p.precision == MAP_FP64; }
 // fine).  `all`: the copies fill every slot's ghost frame; otherwise only
 // the frames the prolongation reads (the step reads same-level neighbour
 // interiors in place).
-map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all, int eonly_sub = -1)
+map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all, int eonly_sub = -1,
+                    const map_dt *dt = nullptr)
 {
     FillArgs a{};
     a.U = U;
-    a.dt = dptr<map_dt>(c, c->ws.dt);
+    a.dt = dt ? dt : dptr<map_dt>(c, c->ws.dt);  // energy-only passes: the subcycle's records
     a.eonly = eonly_sub >= 0;
     a.sub = eonly_sub;
     a.nsims = (int)c->sims.size();
@@ -96,13 +97,14 @@ map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all, int eonly_sub 
 
 // restriction of every parent, finest level first; with cfl, the leaf
 // children's CFL maxima into the per-leaf parts as well
-map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1, bool cfl = false)
+map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1, bool cfl = false,
+                        const map_dt *dt = nullptr)
 {
     RestrictArgs a{};
     a.U = U;
     a.children = dptr<int32_t>(c, c->ws.children);
     a.blk = dptr<BlockRec>(c, c->ws.blocks);
-    a.dt = dptr<map_dt>(c, c->ws.dt);
+    a.dt = dt ? dt : dptr<map_dt>(c, c->ws.dt);  // energy-only passes: the subcycle's records
     a.eonly = eonly_sub >= 0;
     a.sub = eonly_sub;
     a.nsims = (int)c->sims.size();
@@ -317,9 +319,9 @@ map_status run_conduct(map_ctx *c, void *U, void *scratch, const map_dt *dt, hip
         HIPCHK(launch_cond_commit(c->nd, fp64(c), a, s));
         if ((st = run_reflux(c, U, dt, s, i)) != MAP_OK)
             return st;
-        if ((st = run_restrict(c, U, s, i)) != MAP_OK)
+        if ((st = run_restrict(c, U, s, i, false, dt)) != MAP_OK)
             return st;
-        if ((st = run_fill(c, U, s, false, i)) != MAP_OK)
+        if ((st = run_fill(c, U, s, false, i, dt)) != MAP_OK)
             return st;
     }
     return MAP_OK;

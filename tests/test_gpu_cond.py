@@ -92,6 +92,33 @@ def test_subcycle_alone_fp64(dev):
     _check(w, s.state_by_key(), A.state, TOL64, "subcycle alone", ch=[r[0].ch])
 
 
+def test_subcycle_with_caller_records_fp64(dev):
+    """map_conduct takes its sub-step count and length from the records it is
+    given, in every pass (the energy update, reflux, restriction and fill):
+    records with two sub-steps more than map_cfl_dt formed still match the
+    oracle's subcycle with the same records (a pass that kept the count of
+    map_cfl_dt would leave the prolongated ghosts of the last sub-step
+    stale)."""
+    import oracle as orc
+    _say("map_conduct with caller records, 3-D field-aligned")
+    w = _workload(3, "field", seed=13, max_sub=8, kappa0=0.002)
+    s = _sim(w)
+    A = orc.load_workload(w)
+    s.cfl()
+    r = A.cfl()[0]
+    assert 2 <= r.nsub <= 6
+    r.nsub += 2
+    r.dt_sub = r.dt / r.nsub
+    dt = s.dt.clone()
+    dt[0, 4] = r.dt_sub
+    dt[0].view(torch.int32)[10] = r.nsub
+    s.dt.copy_(dt)
+    s.conduct()
+    orc.lib().orc_amr_conduct(A.h, (orc.DtRec * 1)(r))
+    s.sync()
+    _check(w, s.state_by_key(), A.state, TOL64, "subcycle with caller records", ch=[r.ch])
+
+
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_conduction_conserves_energy(dev, ndim):
     """Plain GLM, periodic tree: the eight MHD totals stay constant over
