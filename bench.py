@@ -114,6 +114,36 @@ def step_sources_hash():
     return h.hexdigest()[:16]
 
 
+def library_sources_hash():
+    """Hash of every source of the library (the cycle runs kernels of all of
+    them)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1204_5849_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_cycle_bytes(workload_name):
+    """HBM bytes of one whole cycle (all its dispatches) from the committed
+    counter summary, if it was taken on the current library sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload_name}_fp32_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("cycle_traffic:"):
+            for kv in line.split()[1:]:
+                k, v = kv.split("=")
+                vals[k] = v
+    if vals.get("sources") != library_sources_hash() or "bytes" not in vals:
+        return None
+    return int(vals["bytes"])
+
+
 def measured_valu_busy(workload_name):
     """VALU busy fraction of the step kernel from the committed SQ-counter
     summary, if it was taken on the current step-kernel sources (else None)."""
@@ -485,6 +515,8 @@ def main():
         "hbm_frac_cycle_gather": nleaf_cells * gather_bytes_per_cell(wl, word) / (ms * 1e-3)
         / 1e9 / HBM_PEAK_GBS,
     }
+    cb = measured_cycle_bytes(wl.name) if args.precision == "fp32" else None
+    result["hbm_frac_cycle_measured"] = (cb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if cb else None
 
     if not args.no_regrid:
         log("one regrid of the timed state (estimate, tree edit, remap)")
