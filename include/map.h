@@ -238,7 +238,7 @@ map_status map_status_flags(map_ctx *ctx, uint64_t counters[4], void *stream);
  * shadow state, and an odd nsteps ends with one device copy back into U;
  * WENO cycles update U in place (the shadow holds the stage).  On return U
  * holds the interiors of every block and its prolongated ghosts; the
- * same-level ghost regions of leaves hold unspecified values
+ * same-level ghost regions of leaves and of parents hold unspecified values
  * (map_fill_ghosts refreshes them).  Eager launches on `stream`. */
 map_status map_advance(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
 

@@ -69,6 +69,7 @@ map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all, int eonly_sub 
     a.blk = dptr<BlockRec>(c, c->ws.blocks);
     a.parent = dptr<int32_t>(c, c->ws.parent);
     a.copy_list = all ? nullptr : dptr<int32_t>(c, c->ws.frame_list);
+    a.copy_sel = all ? nullptr : dptr<FrameSel>(c, c->ws.frame_sel);
     const int ncopy = all ? c->nslots : (int)c->frame_list.size();
     const int bpw = fill_blocks_per_group(c->nd);
     if (c->launch_mode == MAP_LAUNCH_PER_BLOCK) {
@@ -89,6 +90,7 @@ map_status run_fill(map_ctx *c, void *U, hipStream_t s, bool all, int eonly_sub 
         if (hi <= lo)
             continue;
         a.list = dptr<int32_t>(c, c->ws.prolong_list) + lo;
+        a.list_mask = dptr<uint32_t>(c, c->ws.prolong_mask) + lo;
         a.nitems = hi - lo;
         HIPCHK(launch_prolong_ghosts(c->nd, fp64(c), a, s));
     }
@@ -517,7 +519,9 @@ map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
     HIPCHK(up(c->ws.orphan_idx, c->orphan_idx.data(), c->orphan_idx.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.restrict_list, c->restrict_list.data(), c->restrict_list.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.prolong_list, c->prolong_list.data(), c->prolong_list.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.prolong_mask, c->prolong_mask.data(), c->prolong_mask.size() * sizeof(uint32_t)));
     HIPCHK(up(c->ws.frame_list, c->frame_list.data(), c->frame_list.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.frame_sel, c->frame_sel.data(), c->frame_sel.size() * sizeof(FrameSel)));
     HIPCHK(up(c->ws.reflux_slots, c->reflux_slots.data(), c->reflux_slots.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.reflux_start, c->reflux_start.data(), c->reflux_start.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.reflux_recs, c->reflux_recs.data(), c->reflux_recs.size() * sizeof(RefluxRec)));

@@ -96,6 +96,10 @@ __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
     int first, stride, end;
     xcd_range(a.nitems, first, stride, end);
     for (int item = first; item < end; item += stride) {
+        // one block per item (3-D): its selection is loaded once
+        FrameSel f1{~0u, {-NG, -NG, -NG}, {NB + NG - 1, NB + NG - 1, NB + NG - 1}, 0};
+        if (BPW == 1 && a.copy_sel && a.slot_base + item < a.slot_end)
+            f1 = a.copy_sel[a.slot_base + item];
         for (int g = threadIdx.x; g < BPW * NGC; g += NTA) {
             const int lb = g / NGC, gi = g - lb * NGC;
             const int i = a.slot_base + item * BPW + lb;
@@ -106,7 +110,14 @@ __global__ void __launch_bounds__(NTA) k_fill_copy(FillArgs a)
                 continue;
             int x, y, z;
             ghost_xyz<NDIM>(gi, x, y, z);
-            const Desc ds = a.desc[(size_t)slot * NDIR + dir_index<NDIM>(x, y, z)];
+            const int di = dir_index<NDIM>(x, y, z);
+            if (BPW == 1 || a.copy_sel) {
+                const FrameSel &f = BPW == 1 ? f1 : a.copy_sel[i];
+                if (!((f.dirs >> di) & 1u) || x < f.lo[0] || x > f.hi[0] || y < f.lo[1] ||
+                    y > f.hi[1] || (NDIM == 3 && (z < f.lo[2] || z > f.hi[2])))
+                    continue;
+            }
+            const Desc ds = a.desc[(size_t)slot * NDIR + di];
             if (ds.src < 0)
                 continue;
             const int sx = src_index(x, ds.o0), sy = src_index(y, ds.o1);
@@ -174,11 +185,12 @@ __global__ void __launch_bounds__(NTA) k_prolong_ghosts(FillArgs a)
         const int cpos = a.blk[slot].cpos;
         const T *pu = U + (size_t)par * NV * P;
         T *ub = U + (size_t)slot * NV * P;
+        // the directions whose descriptor has no source, loaded once per block
+        const uint32_t pm = a.list_mask[item];
         for (int g = threadIdx.x; g < NGC; g += NTA) {
             int x, y, z;
             ghost_xyz<NDIM>(g, x, y, z);
-            const Desc ds = a.desc[(size_t)slot * NDIR + dir_index<NDIM>(x, y, z)];
-            if (ds.src != -1)
+            if (!((pm >> dir_index<NDIM>(x, y, z)) & 1u))
                 continue;
             T v[NV];
             prolong_cell<NDIM, T, K0, K1>(pu, cpos, x, y, z, v);

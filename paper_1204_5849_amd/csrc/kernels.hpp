@@ -39,7 +39,9 @@ struct FillArgs {
     const BlockRec *blk;
     const int32_t *parent;
     const int32_t *list;       // prolongation: slots of the launch
+    const uint32_t *list_mask; // prolongation: prolongated ghost directions per list entry
     const int32_t *copy_list;  // copies: slots (null: slot = index)
+    const FrameSel *copy_sel;  // copies: ghost cells to fill per list entry (null: all)
     int slot_base, slot_end, nitems;  // copies: index range [slot_base, slot_end)
     const map_dt *dt;
     int eonly, sub, nsims;

@@ -32,6 +32,14 @@ struct Desc {
     int src, o0, o1, o2;
 };
 
+// the part of a parent's ghost frame that a fill by copies writes: ghost
+// cells of the directions set in `dirs` inside the padded-cell box [lo, hi]
+struct FrameSel {
+    uint32_t dirs;
+    int lo[3], hi[3];
+    int pad;
+};
+
 // one coarse face next to finer leaves: dimension, side, face buffer of the
 // coarse block and of the 2^(d-1) fine blocks, ordered by transverse halves
 struct RefluxRec {
@@ -47,7 +55,7 @@ struct SimRec {
 // byte offsets of the tables inside the caller's workspace
 struct WsLayout {
     size_t blocks, desc, parent, children, fbidx, leaves, leaf_of, orphans, orphan_idx,
-        restrict_list, prolong_list, frame_list, reflux_slots, reflux_start, reflux_recs, sims,
+        restrict_list, prolong_list, prolong_mask, frame_list, frame_sel, reflux_slots, reflux_start, reflux_recs, sims,
         lvl_dx, dt, dt2, cfl_part,
         cond_part, tot_part, counters, fbuf, remap, newlist, shadow, total;
 };

@@ -5,6 +5,7 @@
 #include "plan.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
@@ -367,17 +368,21 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
     }
     c->restrict_off[lmax + 1] = (int)c->restrict_list.size();
     c->prolong_list.clear();
+    c->prolong_mask.clear();
     c->prolong_off.assign(lmax + 2, 0);
     for (int l = 1; l <= lmax; l++) {
         c->prolong_off[l] = (int)c->prolong_list.size();
         for (int s = 0; s < n; s++) {
             if (c->blk[s].level != l)
                 continue;
-            bool any = false;
+            uint32_t m = 0;
             for (int di = 0; di < NDIR; di++)
-                any |= c->desc[(size_t)s * NDIR + di].src == -1;
-            if (any)
+                if (di != 13 && c->desc[(size_t)s * NDIR + di].src == -1)
+                    m |= 1u << di;
+            if (m) {
                 c->prolong_list.push_back(s);
+                c->prolong_mask.push_back(m);
+            }
         }
     }
     c->prolong_off[lmax + 1] = (int)c->prolong_list.size();
@@ -393,6 +398,64 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
         for (int s = 0; s < n; s++)
             if (mark[s])
                 c->frame_list.push_back(s);
+    }
+    // the ghost cells of those parent tiles that the stencil of the
+    // minmod-limited prolongation reads, as the directions they lie in and
+    // their bounding box: fine ghost cell f (per dimension, counted from the
+    // parent's lowest interior cell) takes the parent cell floor(f / 2) and
+    // its two neighbours along each dimension in turn
+    {
+        auto fdiv2 = [](int v) { return v >= 0 ? v / 2 : -((1 - v) / 2); };
+        // bit b of the result: dimension range [lo, hi] meets side b - 1
+        // (below the interior, inside it, above it)
+        auto sides = [](int lo, int hi) {
+            return (lo < 0 ? 1u : 0u) | (lo < NB && hi >= 0 ? 2u : 0u) | (hi >= NB ? 4u : 0u);
+        };
+        std::vector<uint32_t> mask(n, 0);
+        std::vector<std::array<int, 6>> box(n, {NB, NB, NB, -1, -1, -1});
+        for (int s : c->prolong_list) {
+            const int p = c->parent[s];
+            if (p < 0)
+                continue;
+            const int cpos = c->blk[s].cpos;
+            for (int di = 0; di < NDIR; di++) {
+                if (di == 13 || c->desc[(size_t)s * NDIR + di].src != -1)
+                    continue;
+                const int dir[3] = {di % 3 - 1, (di / 3) % 3 - 1, di / 9 - 1};
+                int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+                for (int d = 0; d < nd; d++) {
+                    const int base = ((cpos >> d) & 1) * NB;
+                    const int a = dir[d] < 0 ? -NG : (dir[d] > 0 ? NB : 0);
+                    const int b = dir[d] < 0 ? -1 : (dir[d] > 0 ? NB + NG - 1 : NB - 1);
+                    lo[d] = fdiv2(base + a);
+                    hi[d] = fdiv2(base + b);
+                }
+                for (int e = -1; e < nd; e++) {  // the centre cells, then each dimension's pair
+                    uint32_t sd[3];
+                    for (int d = 0; d < 3; d++) {
+                        sd[d] = d < nd ? sides(lo[d] - (d == e), hi[d] + (d == e)) : 2u;
+                        box[p][d] = std::min(box[p][d], lo[d] - (d == e));
+                        box[p][3 + d] = std::max(box[p][3 + d], hi[d] + (d == e));
+                    }
+                    for (int z = 0; z < 3; z++)
+                        for (int y = 0; y < 3; y++)
+                            for (int x = 0; x < 3; x++)
+                                if ((sd[0] >> x & 1) && (sd[1] >> y & 1) && (sd[2] >> z & 1) &&
+                                    z * 9 + y * 3 + x != 13)
+                                    mask[p] |= 1u << (z * 9 + y * 3 + x);
+                }
+            }
+        }
+        c->frame_sel.clear();
+        for (int s : c->frame_list) {
+            FrameSel f{};
+            f.dirs = mask[s];
+            for (int d = 0; d < 3; d++) {
+                f.lo[d] = box[s][d];
+                f.hi[d] = box[s][3 + d];
+            }
+            c->frame_sel.push_back(f);
+        }
     }
 
     // ---- reflux: coarse leaf faces whose same-level neighbour has children
@@ -482,7 +545,9 @@ void map_plan_layout(map_ctx *c)
     L.orphan_idx = take(c->orphan_idx.size() * sizeof(int32_t));
     L.restrict_list = take(c->restrict_list.size() * sizeof(int32_t));
     L.prolong_list = take(c->prolong_list.size() * sizeof(int32_t));
+    L.prolong_mask = take(c->prolong_mask.size() * sizeof(uint32_t));
     L.frame_list = take(c->frame_list.size() * sizeof(int32_t));
+    L.frame_sel = take(c->frame_sel.size() * sizeof(FrameSel));
     L.reflux_slots = take(c->reflux_slots.size() * sizeof(int32_t));
     L.reflux_start = take(c->reflux_start.size() * sizeof(int32_t));
     L.reflux_recs = take(c->reflux_recs.size() * sizeof(RefluxRec));

@@ -30,8 +30,12 @@ struct map_ctx {
     std::vector<int> restrict_off;         // [lmax + 1] offsets by level
     std::vector<int32_t> prolong_list;     // slots with prolongated ghosts, by level
     std::vector<int> prolong_off;          // [lmax + 2]
+    std::vector<uint32_t> prolong_mask;    // per prolong_list entry: bit d set if ghost
+                                           // direction d is prolongated
     std::vector<int32_t> frame_list;       // parents of prolong_list slots (their ghost
                                            // frames feed the prolongation), slot order
+    std::vector<mapk::FrameSel> frame_sel; // per frame_list entry: the ghost cells the
+                                           // prolongation stencil reads (a superset)
     std::vector<int32_t> reflux_slots;     // coarse leaves with reflux faces
     std::vector<int32_t> reflux_start;     // [n + 1] into reflux_recs
     std::vector<mapk::RefluxRec> reflux_recs;
