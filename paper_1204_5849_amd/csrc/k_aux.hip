@@ -31,6 +31,18 @@ struct FG<3> {
 };
 constexpr int NTA = 256;
 
+// two adjacent values along x (8- or 16-byte aligned at even padded indices)
+template <typename T>
+struct Pair;
+template <>
+struct Pair<float> {
+    using V = float2;
+};
+template <>
+struct Pair<double> {
+    using V = double2;
+};
+
 // g-th ghost cell of a block, enumerated in the padded tile's linear order
 // by regions: the ghost planes/rows below and above, then the side strips
 template <int NDIM>
@@ -167,10 +179,57 @@ __device__ __forceinline__ void prolong_cell(const T *pu, int cpos, int x, int y
 }
 
 // ---- prolongated ghosts of the blocks of one level (descriptor src == -1)
+// Every ghost region of a child is a union of 2^d-cell groups whose fine
+// cells lie in one parent cell: the group shares that cell's value and
+// limited slopes, and its cells differ only in the signs of the quarter-
+// slope terms.  One thread forms a whole group (the operations of
+// prolong_cell, in its order, per fine cell) and stores it as x pairs.
+// Groups are enumerated over the child's padded tile at parent resolution
+// (10^d cells, the 8^d interior ones skipped): the planes below and above,
+// then the rows, then the columns.
+template <int NDIM>
+__device__ __forceinline__ void group_xyz(int g, int &X, int &Y, int &Z)
+{
+    constexpr int H = NB / 2, Q = H + 2;  // interior and padded groups per dimension
+    if constexpr (NDIM == 2) {
+        Z = 0;
+        if (g < 2 * Q) {
+            const int r = g / Q;
+            X = g - r * Q - 1;
+            Y = r ? H : -1;
+        } else {
+            g -= 2 * Q;
+            Y = g >> 1;
+            X = (g & 1) ? H : -1;
+        }
+    } else {
+        if (g < 2 * Q * Q) {
+            const int pl = g / (Q * Q), r = g - pl * Q * Q;
+            Z = pl ? H : -1;
+            Y = r / Q - 1;
+            X = r % Q - 1;
+        } else if (g < 2 * Q * Q + H * 2 * Q) {
+            g -= 2 * Q * Q;
+            Z = g / (2 * Q);
+            const int r = g - Z * 2 * Q;
+            Y = r < Q ? -1 : H;
+            X = r % Q - 1;
+        } else {
+            g -= 2 * Q * Q + H * 2 * Q;
+            Z = g / (2 * H);
+            const int r = g - Z * 2 * H;
+            Y = r >> 1;
+            X = (r & 1) ? H : -1;
+        }
+    }
+}
+
 template <int NDIM, typename T, bool EO>
 __global__ void __launch_bounds__(NTA) k_prolong_ghosts(FillArgs a)
 {
-    constexpr int P = FG<NDIM>::P, NGC = FG<NDIM>::NGC;
+    using V = typename Pair<T>::V;
+    constexpr int P = FG<NDIM>::P, H = NB / 2, Q = H + 2;
+    constexpr int NGG = NDIM == 3 ? Q * Q * Q - H * H * H : Q * Q - H * H;  // ghost groups
     constexpr int K0 = VarRange<EO>::K0, K1 = VarRange<EO>::K1;
     T *U = (T *)a.U;
     if (EO && sub_idle(a.dt, a.nsims, a.sub))
@@ -187,17 +246,46 @@ __global__ void __launch_bounds__(NTA) k_prolong_ghosts(FillArgs a)
         T *ub = U + (size_t)slot * NV * P;
         // the directions whose descriptor has no source, loaded once per block
         const uint32_t pm = a.list_mask[item];
-        for (int g = threadIdx.x; g < NGC; g += NTA) {
-            int x, y, z;
-            ghost_xyz<NDIM>(g, x, y, z);
+        for (int g = threadIdx.x; g < NGG; g += NTA) {
+            int X, Y, Z;
+            group_xyz<NDIM>(g, X, Y, Z);
+            const int x = 2 * X, y = 2 * Y, z = NDIM == 3 ? 2 * Z : 0;
             if (!((pm >> dir_index<NDIM>(x, y, z)) & 1u))
                 continue;
-            T v[NV];
-            prolong_cell<NDIM, T, K0, K1>(pu, cpos, x, y, z, v);
-            const int c = lin<NDIM>(x, y, z);
+            // the parent cell of the group
+            const int c = lin<NDIM>((cpos & 1) * H + X, ((cpos >> 1) & 1) * H + Y,
+                                    NDIM == 3 ? ((cpos >> 2) & 1) * H + Z : 0);
+            const int st[3] = {1, PD, PD * PD};
+            const int f0 = lin<NDIM>(x, y, z);
 #pragma unroll
-            for (int k = K0; k < K1; k++)
-                ub[(size_t)k * P + c] = v[k];
+            for (int k = K0; k < K1; k++) {
+                const T *q = pu + (size_t)k * P;
+                const T val = q[c];
+                T sw[3];  // quarter slope along each dimension
+#pragma unroll
+                for (int d = 0; d < NDIM; d++)
+                    sw[d] = lim_minmod(q[c + st[d]] - val, val - q[c - st[d]]) * T(0.25);
+                T *o = ub + (size_t)k * P + f0;
+#pragma unroll
+                for (int j = 0; j < (NDIM == 3 ? 4 : 2); j++) {
+                    const int jy = j & 1, jz = j >> 1;  // fine cell 2Y + jy, 2Z + jz
+                    // v = ((val + s0 w0) + s1 w1) + s2 w2 with w = -1/4 (even
+                    // fine index) or +1/4 (odd); -s/4 is exact
+                    T lo = val - sw[0], hi = val + sw[0];
+                    const T ty = jy ? sw[1] : -sw[1];
+                    lo = lo + ty;
+                    hi = hi + ty;
+                    if constexpr (NDIM == 3) {
+                        const T tz = jz ? sw[2] : -sw[2];
+                        lo = lo + tz;
+                        hi = hi + tz;
+                    }
+                    V pr;
+                    pr.x = lo;
+                    pr.y = hi;
+                    *reinterpret_cast<V *>(o + jy * PD + (NDIM == 3 ? jz * PD * PD : 0)) = pr;
+                }
+            }
         }
     }
 }
@@ -232,17 +320,6 @@ __global__ void __launch_bounds__(NTA) k_prolong_blocks(FillArgs a)
 // (Sec. 4.2, Sec. 4.3 step 1).  The two cells of an x pair are adjacent and
 // 2-element aligned in the padded tile, so each pair is one vector load; the
 // sum is taken x pairs first, then y, then z.
-template <typename T>
-struct Pair;
-template <>
-struct Pair<float> {
-    using V = float2;
-};
-template <>
-struct Pair<double> {
-    using V = double2;
-};
-
 // the CFL speed of one cell (Sec. 3.7): max over d of |v_d| + c_f,d, in FP64
 // from its conserved variables; pr takes the gas pressure and bad is set
 // when rho <= 0 or p <= 0
