@@ -665,6 +665,9 @@ __global__ void __launch_bounds__(NTA) k_dt(DtArgs a)
     const SimRec sr = a.sims[s];
     auto sim_max = [&](const double *part) {
         double m = 0.0;
+        // unrolled so that the loads of several iterations are in flight
+        // together (the maximum does not depend on the order)
+#pragma unroll 8
         for (int i = sr.leaf_lo + (int)threadIdx.x; i < sr.leaf_hi; i += NTA)
             m = part[i] > m ? part[i] : m;
 #pragma unroll
