@@ -151,6 +151,18 @@ map_status map_query(const map_ctx *ctx, map_sizes *sizes, int32_t *slot_of_key)
  * (dz+1)*9 + (dy+1)*3 + (dx+1).  Host only. */
 map_status map_neighbors(const map_ctx *ctx, int32_t *neigh);
 
+/* The part of the parents' ghost frames that the fill inside a cycle
+ * refreshes by copies: every parent whose tile the prolongation of ghosts
+ * reads (Sec. 4.3 step 6), with the ghost directions its limited-linear
+ * stencil reaches (bit (dz+1)*9 + (dy+1)*3 + (dx+1) of dirs[i]) and the box
+ * of padded cells that holds every cell it reads (box[i][0..2] = lowest
+ * x, y, z, box[i][3..5] = highest; interior cells are 0..15, ghosts -2, -1,
+ * 16, 17); the copies write the ghost cells of those directions inside the
+ * box.  parent[i] is an input index.  Writes min(cap, count) entries and
+ * the number of such parents to *count.  Host only. */
+map_status map_fill_selection(const map_ctx *ctx, int cap, int32_t *parent, uint32_t *dirs,
+                              int32_t *box, int *count);
+
 /* Bind a caller-owned device workspace of at least workspace_bytes and
  * upload the tables on `stream` (asynchronous).  The workspace must outlive
  * every later call.  Errors: MAP_EINVAL, MAP_ENOMEM, MAP_EHIP. */

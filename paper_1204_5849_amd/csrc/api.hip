@@ -491,6 +491,28 @@ map_status map_neighbors(const map_ctx *c, int32_t *neigh)
     return MAP_OK;
 }
 
+map_status map_fill_selection(const map_ctx *c, int cap, int32_t *parent, uint32_t *dirs,
+                              int32_t *box, int *count)
+{
+    if (!c || !count || cap < 0 || (cap > 0 && (!parent || !dirs || !box)))
+        return fail(MAP_EINVAL, "null argument or negative capacity");
+    std::vector<int32_t> key_of_slot(c->nslots);
+    for (int i = 0; i < c->nslots; i++)
+        key_of_slot[c->slot_of_key[i]] = i;
+    const int n = (int)c->frame_list.size();
+    for (int i = 0; i < n && i < cap; i++) {
+        const FrameSel &f = c->frame_sel[i];
+        parent[i] = key_of_slot[c->frame_list[i]];
+        dirs[i] = f.dirs;
+        for (int d = 0; d < 3; d++) {
+            box[(size_t)i * 6 + d] = f.lo[d];
+            box[(size_t)i * 6 + 3 + d] = f.hi[d];
+        }
+    }
+    *count = n;
+    return MAP_OK;
+}
+
 map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
 {
     if (!c || !ws)

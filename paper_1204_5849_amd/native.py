@@ -31,7 +31,7 @@ PRECISION = {"fp64": MAP_FP64, "fp32": MAP_FP32_MIXED}
 RIEMANN = {"rusanov": MAP_RUSANOV, "hllc": MAP_HLLC}
 COND = {"off": MAP_COND_OFF, "iso": MAP_COND_ISO, "field": MAP_COND_FIELD}
 
-EXPORTS = ["map_init_blocks", "map_query", "map_neighbors", "map_bind_workspace",
+EXPORTS = ["map_init_blocks", "map_query", "map_neighbors", "map_fill_selection", "map_bind_workspace",
            "map_prim_to_cons", "map_fill_ghosts", "map_restrict", "map_prolong", "map_cfl_dt",
            "map_step", "map_reflux", "map_conduct", "map_totals", "map_status_flags", "map_advance",
            "map_graph_run", "map_set_launch", "map_autotune", "map_estimate", "map_regrid",
@@ -106,6 +106,8 @@ def lib():
                                       C.POINTER(map_sim_desc), C.c_int, C.POINTER(map_block_key)]
         L.map_query.argtypes = [vp, C.POINTER(map_sizes), C.POINTER(C.c_int32)]
         L.map_neighbors.argtypes = [vp, C.POINTER(C.c_int32)]
+        L.map_fill_selection.argtypes = [vp, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_uint32),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int)]
         L.map_bind_workspace.argtypes = [vp, vp, C.c_size_t, vp]
         L.map_prim_to_cons.argtypes = [vp, vp, vp]
         L.map_fill_ghosts.argtypes = [vp, vp, vp]
@@ -212,6 +214,20 @@ def map_neighbors(ctx, nblocks):
     out = np.zeros((nblocks, 27), dtype=np.int32)
     check(lib().map_neighbors(ctx, out.ctypes.data_as(C.POINTER(C.c_int32))))
     return out
+
+
+def map_fill_selection(ctx):
+    """(parent input indices, direction masks, boxes [n, 6]) of the cycle's fill."""
+    import numpy as np
+    n = C.c_int()
+    check(lib().map_fill_selection(ctx, 0, None, None, None, C.byref(n)))
+    par = np.zeros(n.value, dtype=np.int32)
+    dirs = np.zeros(n.value, dtype=np.uint32)
+    box = np.zeros((n.value, 6), dtype=np.int32)
+    check(lib().map_fill_selection(ctx, n.value, par.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   dirs.ctypes.data_as(C.POINTER(C.c_uint32)),
+                                   box.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)))
+    return par, dirs, box
 
 
 def map_bind_workspace(ctx, ws, nbytes, stream):

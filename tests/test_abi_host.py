@@ -1,6 +1,7 @@
 """Host-side tests of libmap.so (no GPU): exported symbols, block-tree
-validation errors, Morton slot order and the neighbour tables against a
-brute-force geometric search."""
+validation errors, Morton slot order, the neighbour tables against a
+brute-force geometric search and the cycle's fill selection against the
+cells the prolongation reads."""
 import os
 import re
 
@@ -174,6 +175,68 @@ def test_neighbours_match_brute_force(ndim, bc):
                         src.append(G // n)
                     want = index.get((s, lv, *src), -1)
                     assert got[i, di] == want, (i, (dx, dy, dz))
+
+
+@pytest.mark.parametrize("ndim,bc,seed", [(2, "periodic", 3), (2, "outflow", 4), (3, "periodic", 5),
+                                          (3, "mixed", 6)])
+def test_fill_selection_is_what_the_prolongation_reads(ndim, bc, seed):
+    """The parent ghost cells a cycle's fill refreshes: every parent cell that
+    the limited-linear prolongation (Sec. 4.3 step 6) reads for the ghost
+    regions without a same-level source, found by enumerating those fine
+    ghost cells, is inside the selection, whose directions and box are
+    exactly those of the cells read."""
+    rng = np.random.default_rng(seed)
+    nb = (3, 2, 1) if ndim == 2 else (2, 2, 2)
+    if bc == "mixed":
+        bcs = (("periodic", "periodic"), ("outflow", "outflow"), ("periodic", "periodic"))
+    else:
+        bcs = ((bc, bc),) * 3
+    sims = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb, bc=bcs)]
+    keys = random_tree(sims, ndim, 3, 0.4, rng)
+    ctx = N.map_init_blocks(N.make_params(ndim), sims, keys)
+    neigh = N.map_neighbors(ctx, len(keys))
+    par, dirs, box = N.map_fill_selection(ctx)
+    N.map_destroy(ctx)
+    n, ng = 16, 2
+    index = {tuple(k): i for i, k in enumerate(keys.tolist())}
+    want = {}  # parent -> list of arrays of read parent cells [m, 3]
+    for i, (s, lv, kx, ky, kz) in enumerate(keys.tolist()):
+        pro = [d for d in range(27) if d != 13 and neigh[i, d] == -1]
+        if not pro:
+            continue
+        p = index[(s, lv - 1, kx >> 1, ky >> 1, kz >> 1)]
+        cpos = (kx & 1, ky & 1, kz & 1)
+        for d in pro:
+            dd = (d % 3 - 1, (d // 3) % 3 - 1, d // 9 - 1)
+            axes = []
+            for a in range(3):
+                if a >= ndim:
+                    axes.append(np.array([0]))
+                else:
+                    axes.append({-1: np.arange(-ng, 0), 0: np.arange(0, n), 1: np.arange(n, n + ng)}[dd[a]])
+            f = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, 3)
+            c = f.copy()
+            for a in range(ndim):
+                c[:, a] = np.floor_divide(cpos[a] * n + f[:, a], 2)
+            reads = [c]
+            for a in range(ndim):
+                for sgn in (-1, 1):
+                    e = c.copy()
+                    e[:, a] += sgn
+                    reads.append(e)
+            want.setdefault(p, []).extend(reads)
+    assert sorted(par.tolist()) == sorted(want)
+    assert len(set(par.tolist())) == len(par)
+    for p, m, b in zip(par.tolist(), dirs.tolist(), box.tolist()):
+        cells = np.unique(np.concatenate(want[p]), axis=0)
+        assert cells.min() >= -ng and cells.max() <= n + ng - 1
+        side = np.where(cells < 0, 0, np.where(cells >= n, 2, 1))
+        side[:, ndim:] = 1
+        di = side[:, 2] * 9 + side[:, 1] * 3 + side[:, 0]
+        got_dirs = {k for k in range(27) if (m >> k) & 1}
+        assert got_dirs == set(di[di != 13].tolist()), p
+        lo, hi = cells.min(axis=0), cells.max(axis=0)
+        assert b[:ndim] == lo[:ndim].tolist() and b[3:3 + ndim] == hi[:ndim].tolist(), p
 
 
 def test_each_step_instance_is_compiled_once():
