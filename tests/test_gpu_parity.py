@@ -221,6 +221,66 @@ def test_graph_equals_eager_and_per_block_equals_batched(dev):
     assert np.array_equal(a2, b.state_by_key())
 
 
+@pytest.mark.parametrize("case", ["tree2d", "tree3d", "harris3d"])
+def test_cycle_fill_writes_what_a_full_fill_writes(dev, case):
+    """The fill inside a cycle copies only the parent ghost cells that the
+    prolongation stencil reads (map_fill_selection) and then prolongates:
+    a full ghost fill afterwards leaves those parent cells and every
+    prolongated ghost cell of every block unchanged, bit for bit.  On the
+    random trees the selection is mostly whole frames; on the Harris sheet
+    (refined slabs) it is the planes next to the coarse side."""
+    _say(f"cycle fill against a full fill: {case}")
+    if case == "harris3d":
+        w = W.harris3d(nbase=2, levels=3, precision="fp64")
+    else:
+        ndim = 2 if case == "tree2d" else 3
+        sims, keys = _tree(ndim, 21 + ndim, "mixed")
+        w = W.Workload(name="tree", ndim=ndim, sims=sims, keys=keys, ic=_tree_ic)
+    ndim, keys = w.ndim, w.keys
+    s = _sim(w)
+    s.advance(3)
+    a = s.state_by_key()
+    par, dirs, box = N.map_fill_selection(s.ctx)
+    neigh = N.map_neighbors(s.ctx, len(keys))
+    s.fill()
+    b = s.state_by_key()
+    assert len(par) > 0
+    n, ng = 16, 2
+    c = np.arange(-ng, n + ng)
+    if ndim == 3:
+        z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    else:
+        y, x = np.meshgrid(c, c, indexing="ij")
+        y, x = y[None], x[None]
+        z = np.zeros_like(x)
+    assert x.shape == a.shape[2:]
+
+    def side(v):
+        return np.where(v < 0, 0, np.where(v >= n, 2, 1))
+
+    di = side(z) * 9 + side(y) * 3 + side(x)
+    partial = 0
+    for p, m, bx in zip(par.tolist(), dirs.tolist(), box.tolist()):
+        sel = (np.right_shift(m, di) & 1).astype(bool) & (di != 13)
+        sel &= (x >= bx[0]) & (x <= bx[3]) & (y >= bx[1]) & (y <= bx[4])
+        if ndim == 3:
+            sel &= (z >= bx[2]) & (z <= bx[5])
+        assert sel.any()
+        partial += int(sel.sum() < (di != 13).sum())
+        assert np.array_equal(a[p][:, sel], b[p][:, sel]), p
+    if case == "harris3d":
+        assert partial == len(par)  # every frame is filled in part
+    nprol = 0
+    for i in range(len(keys)):
+        pro = [d for d in range(27) if d != 13 and neigh[i, d] == -1]
+        if pro:
+            nprol += 1
+            sel = np.isin(di, pro)
+            assert np.array_equal(a[i][:, sel], b[i][:, sel]), i
+    assert nprol > 0
+    _say(f"{len(par)} parents, {partial} with partial frames, {nprol} blocks with prolongated ghosts")
+
+
 @pytest.mark.parametrize("ndim,scheme,precision", [(2, "lf", "fp64"), (3, "lf", "fp64"),
                                                     (3, "weno", "fp64"), (3, "lf", "fp32")])
 def test_cycles_in_one_call_equal_cycle_by_cycle(dev, ndim, scheme, precision):
