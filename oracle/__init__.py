@@ -45,7 +45,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
-                               "-Wall", "-Wno-unused-function", "-shared", "-fPIC",
+                               "-fopenmp", "-Wall", "-Wno-unused-function", "-shared", "-fPIC",
                                "-o", tmp, src, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -92,6 +92,8 @@ def lib():
         pp = C.POINTER(Params)
         ip = C.POINTER(C.c_int)
         lp = C.POINTER(C.c_long)
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.restype = C.c_int
         L.orc_nvar.argtypes = [pp]
         L.orc_pressure.argtypes = [pp, dp]
         L.orc_pressure.restype = C.c_double
@@ -106,6 +108,7 @@ def lib():
         L.orc_weno_face.restype = C.c_double
         L.orc_prim_to_cons.argtypes = [pp, dp, C.c_long]
         L.orc_step_tile.argtypes = [pp, dp, dp, ip, C.POINTER(DtRec), dp, dp, lp]
+        L.orc_lf_states.argtypes = [pp, dp, dp, ip, C.POINTER(DtRec), dp, dp, dp, lp]
         L.orc_eglm_source.argtypes = [pp, dp, dp, ip, dp]
         L.orc_resistive.argtypes = [pp, dp, dp, ip, dp]
         L.orc_tile_maxspeed.argtypes = [pp, dp, ip]
@@ -138,6 +141,16 @@ def lib():
         L.orc_estimate.restype = C.c_double
         _lib = L
     return _lib
+
+
+def set_threads(n: int) -> None:
+    """Threads of the block-tree loops (default 1); any count gives the
+    one-thread result bit for bit."""
+    lib().orc_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().orc_get_threads())
 
 
 def _dp(a: np.ndarray):
@@ -290,6 +303,25 @@ def step_tile(p, dx, u, n, rec: DtRec, want_faces=False):
                         cnt.ctypes.data_as(C.POINTER(C.c_long)))
     shape = (nv, n3[2], n3[1], n3[0])
     return unew.reshape(shape), ff, cnt
+
+
+def lf_states(p, dx, u, n, rec: DtRec):
+    """Intermediate states of the LF scheme on a padded tile: (u~ [nv, pz, py,
+    px], slopes [ndim, nv, pz, py, px], face states [ndim, 2, nv, pz, py, px]
+    (left, right; face c+1/2 stored at cell c), counters)."""
+    n3 = _n3(p, n)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    shape = tile_shape(p, n3)
+    nd = p.ndim
+    ut = np.zeros(shape)
+    sl = np.zeros((nd,) + shape)
+    lr = np.zeros((nd, 2) + shape)
+    dxa = np.array(list(dx) + [1.0] * (3 - len(dx)), dtype=np.float64)
+    cnt = np.zeros(4, dtype=np.int64)
+    n3c, n3p = _ip(n3)
+    lib().orc_lf_states(C.byref(p), _dp(dxa), _dp(u), n3p, C.byref(rec), _dp(ut), _dp(sl),
+                        _dp(lr), cnt.ctypes.data_as(C.POINTER(C.c_long)))
+    return ut, sl, lr, cnt
 
 
 def eglm_source(p, dx, u, n):

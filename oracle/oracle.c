@@ -20,6 +20,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 enum { RHO = 0, MX = 1, MY = 2, MZ = 3, BX = 4, BY = 5, BZ = 6, EN = 7, PSI = 8 };
 #define NVMAX 9
@@ -66,6 +69,15 @@ static long interior_index(const geo *G, int x, int y, int z)
 /* pointwise physics                                                   */
 /* ------------------------------------------------------------------ */
 int orc_nvar(const orc_params *p) { return p->physics == ORC_MHD ? 9 : 1; }
+
+/* Threads of the block-tree loops (orc_amr_*).  Each block's arithmetic is
+ * the same whichever thread runs it and no reduction order depends on the
+ * thread count (maxima are exact, the totals stay serial), so every result
+ * is bit for bit the one-thread result.  Default 1. */
+static int g_threads = 1;
+
+void orc_set_threads(int n) { g_threads = n < 1 ? 1 : n; }
+int orc_get_threads(void) { return g_threads; }
 
 /* p = (gamma-1)(e - rho v^2/2 - B^2/2)   (Sec. 2, below MHD-04) */
 double orc_pressure(const orc_params *p, const double *u)
@@ -447,7 +459,8 @@ void orc_face_flux(const orc_params *p, const double *L, const double *R, int d,
 /* LF corrector fluxes (limiter2 + Equ:LFFlux) on every face of dimension d
  * that bounds an interior cell; the face c+1/2 is stored at index c. */
 static void lf_faces(const orc_params *p, const geo *G, const double *ut,
-                     const double *sl, int d, double ch, double *fh, long *cnt)
+                     const double *sl, int d, double ch, double *fh, long *cnt,
+                     double *lr)
 {
     int nv = orc_nvar(p);
     long P = G->P;
@@ -471,6 +484,11 @@ static void lf_faces(const orc_params *p, const geo *G, const double *ut,
                     load(ut, P, nv, cn, R);
                     cnt[1]++;
                 }
+                if (lr)  /* the two states the face flux receives */
+                    for (int k = 0; k < nv; k++) {
+                        lr[k * P + c] = L[k];
+                        lr[((long)nv + k) * P + c] = R[k];
+                    }
                 double fc[NVMAX];
                 orc_face_flux(p, L, R, d, ch, fc);
                 for (int k = 0; k < nv; k++)
@@ -760,7 +778,7 @@ void orc_step_tile(const orc_params *p, const double dx[3], const double *u,
         double *sl = calloc((size_t)nd * nv * P, sizeof(double));
         lf_predict(p, &G, u, hdt, dt->ch, ut, sl, cnt);
         for (int d = 0; d < nd; d++)
-            lf_faces(p, &G, ut, sl, d, dt->ch, fh[d], cnt);
+            lf_faces(p, &G, ut, sl, d, dt->ch, fh[d], cnt, NULL);
         free(ut);
         free(sl);
     } else if (p->scheme == ORC_WENO) {
@@ -839,6 +857,32 @@ void orc_step_tile(const orc_params *p, const double dx[3], const double *u,
     free(res);
     for (int d = 0; d < nd; d++)
         free(fh[d]);
+}
+
+/* The intermediate states of the LF scheme on one padded tile (for the
+ * tests of the positivity fall-back, Sec. 3.2): the predicted state u~ and
+ * the limited slopes on the whole padded tile (zero outside the region the
+ * predictor covers), and, per dimension, the left and right states that the
+ * face flux of each face receives after the fall-back, face c+1/2 stored at
+ * cell c.  Layouts: ut[nvar][P], sl[ndim][nvar][P], lr[ndim][2][nvar][P]. */
+void orc_lf_states(const orc_params *p, const double dx[3], const double *u,
+                   const int n_in[3], const orc_dtrec *dt, double *ut, double *sl,
+                   double *lr, long *cnt)
+{
+    geo G = mkgeo(p->ndim, n_in);
+    int nv = orc_nvar(p), nd = G.nd;
+    long P = G.P;
+    double hdt[3] = {0, 0, 0};
+    for (int d = 0; d < nd; d++)
+        hdt[d] = 0.5 * dt->dt / dx[d];
+    memset(ut, 0, sizeof(double) * nv * P);
+    memset(sl, 0, sizeof(double) * nd * nv * P);
+    memset(lr, 0, sizeof(double) * nd * 2 * nv * P);
+    double *fh = calloc((size_t)nv * P, sizeof(double));
+    lf_predict(p, &G, u, hdt, dt->ch, ut, sl, cnt);
+    for (int d = 0; d < nd; d++)
+        lf_faces(p, &G, ut, sl, d, dt->ch, fh, cnt, lr + (size_t)d * 2 * nv * P);
+    free(fh);
 }
 
 double orc_tile_maxspeed(const orc_params *p, const double *u, const int n_in[3])
@@ -1289,6 +1333,7 @@ static double *tile(orc_amr *A, int b) { return A->U + (size_t)b * A->nv * A->G.
 
 void orc_amr_prim_to_cons(orc_amr *A)
 {
+#pragma omp parallel for schedule(static) num_threads(g_threads)
     for (int b = 0; b < A->nb; b++)
         orc_prim_to_cons(&A->p, tile(A, b), A->G.P);
 }
@@ -1327,70 +1372,79 @@ static void prolong_cell(orc_amr *A, int b, int x, int y, int z, double *out)
     }
 }
 
-typedef struct { int b, x, y, z; } pcell;
+/* the same-level source of ghost cell (x, y, z) of block b (Sec. 4.3 steps
+ * 3-5): the global index at b's level after periodic wrap or outflow
+ * clamping, split into the block that holds it (-1 if no block of b's level
+ * does) and the cell inside that block (lc) */
+static int ghost_source(const orc_amr *A, int b, int x, int y, int z, int lc[3])
+{
+    const orc_key *k = &A->keys[b];
+    const orc_sim *S = &A->sims[k->sim];
+    int kc[3], loc[3] = {x, y, z}, bc3[3] = {0, 0, 0};
+    key_coords(k, kc);
+    lc[0] = lc[1] = lc[2] = 0;
+    for (int d = 0; d < A->nd; d++) {
+        int N = cells_at_level(A, k->sim, d, k->level);
+        int g = map_index(kc[d] * A->n + loc[d], N, S->bc[d][0], S->bc[d][1]);
+        bc3[d] = g / A->n;
+        lc[d] = g - bc3[d] * A->n;
+    }
+    return lookup(A, k->sim, k->level, bc3[0], bc3[1], bc3[2]);
+}
 
+static int is_interior(const geo *G, int x, int y, int z)
+{
+    return x >= 0 && x < G->n[0] && y >= 0 && y < G->n[1] && z >= 0 && z < G->n[2];
+}
+
+/* ghost cells of every block: copies of the same-level source's interior
+ * cells, then, level by level from coarse to fine (so that a parent's own
+ * prolonged ghosts are in place), prolongation from the parent where no
+ * same-level source exists */
 void orc_amr_fill(orc_amr *A)
 {
     geo *G = &A->G;
-    int nv = A->nv, n = A->n;
-    size_t cap = 1024, np = 0;
-    pcell *pl = malloc(sizeof(pcell) * cap);
+    int nv = A->nv;
+#pragma omp parallel for schedule(dynamic, 8) num_threads(g_threads)
     for (int b = 0; b < A->nb; b++) {
-        const orc_key *k = &A->keys[b];
-        const orc_sim *S = &A->sims[k->sim];
-        int kc[3];
-        key_coords(k, kc);
         double *u = tile(A, b);
         for (int z = -G->g[2]; z < G->n[2] + G->g[2]; z++)
             for (int y = -G->g[1]; y < G->n[1] + G->g[1]; y++)
                 for (int x = -G->g[0]; x < G->n[0] + G->g[0]; x++) {
-                    int loc[3] = {x, y, z};
-                    int inside = 1;
-                    for (int d = 0; d < 3; d++)
-                        if (loc[d] < 0 || loc[d] >= G->n[d])
-                            inside = 0;
-                    if (inside)
+                    if (is_interior(G, x, y, z))
                         continue;
-                    int bc3[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
-                    for (int d = 0; d < A->nd; d++) {
-                        int N = cells_at_level(A, k->sim, d, k->level);
-                        int g = map_index(kc[d] * n + loc[d], N, S->bc[d][0], S->bc[d][1]);
-                        bc3[d] = g / n;
-                        lc[d] = g - bc3[d] * n;
-                    }
-                    int src = lookup(A, k->sim, k->level, bc3[0], bc3[1], bc3[2]);
-                    long c = at(G, x, y, z);
-                    if (src >= 0) {
-                        const double *su = tile(A, src);
-                        long sc = at(G, lc[0], lc[1], lc[2]);
-                        for (int kv = 0; kv < nv; kv++)
-                            u[kv * G->P + c] = su[kv * G->P + sc];
-                    } else {
-                        if (np == cap) {
-                            cap *= 2;
-                            pl = realloc(pl, sizeof(pcell) * cap);
-                        }
-                        pl[np].b = b;
-                        pl[np].x = x;
-                        pl[np].y = y;
-                        pl[np].z = z;
-                        np++;
-                    }
+                    int lc[3];
+                    int src = ghost_source(A, b, x, y, z, lc);
+                    if (src < 0)
+                        continue;
+                    const double *su = tile(A, src);
+                    long c = at(G, x, y, z), sc = at(G, lc[0], lc[1], lc[2]);
+                    for (int kv = 0; kv < nv; kv++)
+                        u[kv * G->P + c] = su[kv * G->P + sc];
                 }
     }
-    /* coarse to fine, so a parent's own prolonged ghosts are in place */
-    for (int lv = 2; lv <= A->lmax; lv++)
-        for (size_t i = 0; i < np; i++) {
-            if (A->keys[pl[i].b].level != lv)
+    for (int lv = 2; lv <= A->lmax; lv++) {
+#pragma omp parallel for schedule(dynamic, 8) num_threads(g_threads)
+        for (int b = 0; b < A->nb; b++) {
+            if (A->keys[b].level != lv)
                 continue;
-            double v[NVMAX];
-            prolong_cell(A, pl[i].b, pl[i].x, pl[i].y, pl[i].z, v);
-            double *u = tile(A, pl[i].b);
-            long c = at(G, pl[i].x, pl[i].y, pl[i].z);
-            for (int kv = 0; kv < nv; kv++)
-                u[kv * G->P + c] = v[kv];
+            double *u = tile(A, b);
+            for (int z = -G->g[2]; z < G->n[2] + G->g[2]; z++)
+                for (int y = -G->g[1]; y < G->n[1] + G->g[1]; y++)
+                    for (int x = -G->g[0]; x < G->n[0] + G->g[0]; x++) {
+                        if (is_interior(G, x, y, z))
+                            continue;
+                        int lc[3];
+                        if (ghost_source(A, b, x, y, z, lc) >= 0)
+                            continue;
+                        double v[NVMAX];
+                        prolong_cell(A, b, x, y, z, v);
+                        long c = at(G, x, y, z);
+                        for (int kv = 0; kv < nv; kv++)
+                            u[kv * G->P + c] = v[kv];
+                    }
         }
-    free(pl);
+    }
 }
 
 void orc_amr_prolong_block(orc_amr *A, int b)
@@ -1413,7 +1467,8 @@ void orc_amr_restrict(orc_amr *A)
 {
     geo *G = &A->G;
     int n = A->n, nd = A->nd;
-    for (int lv = A->lmax - 1; lv >= 1; lv--)
+    for (int lv = A->lmax - 1; lv >= 1; lv--) {
+#pragma omp parallel for schedule(dynamic, 8) num_threads(g_threads)
         for (int b = 0; b < A->nb; b++) {
             const orc_key *k = &A->keys[b];
             if (k->level != lv || !A->haskids[b])
@@ -1449,6 +1504,7 @@ void orc_amr_restrict(orc_amr *A)
                         }
                     }
         }
+    }
 }
 
 static void sim_dxmin(const orc_amr *A, int sim, double *dxmin)
@@ -1474,6 +1530,7 @@ void orc_amr_cfl(orc_amr *A, orc_dtrec *out)
     int nn[3] = {A->n, A->n, A->n};
     for (int s = 0; s < A->nsims; s++) {
         double alpha = 0.0, dxmin;
+#pragma omp parallel for schedule(dynamic, 8) reduction(max : alpha) num_threads(g_threads)
         for (int b = 0; b < A->nb; b++) {
             if (A->keys[b].sim != s || A->haskids[b])
                 continue;
@@ -1483,6 +1540,7 @@ void orc_amr_cfl(orc_amr *A, orc_dtrec *out)
         }
         sim_dxmin(A, s, &dxmin);
         double kmax = 0.0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(max : kmax) num_threads(g_threads)
         for (int b = 0; b < A->nb; b++) {
             if (A->keys[b].sim != s || A->haskids[b])
                 continue;
@@ -1496,6 +1554,14 @@ void orc_amr_cfl(orc_amr *A, orc_dtrec *out)
 
 static void amr_weno_rk2(orc_amr *A, const orc_dtrec *dt);
 
+static void add_counters(orc_amr *A, const long cnt[4])
+{
+    for (int i = 0; i < 4; i++) {
+#pragma omp atomic
+        A->cnt[i] += cnt[i];
+    }
+}
+
 void orc_amr_step(orc_amr *A, const orc_dtrec *dt)
 {
     if (A->p.scheme == ORC_WENO) {
@@ -1504,22 +1570,29 @@ void orc_amr_step(orc_amr *A, const orc_dtrec *dt)
     }
     geo *G = &A->G;
     int nn[3] = {A->n, A->n, A->n};
-    double *unew = malloc(sizeof(double) * A->nv * G->I);
-    for (int b = 0; b < A->nb; b++) {
-        if (A->haskids[b])
-            continue;
-        double dx[3];
-        block_dx(A, b, dx);
-        double *u = tile(A, b);
-        double *ff = A->ff + (size_t)b * 2 * A->nd * A->nv * A->T;
-        orc_step_tile(&A->p, dx, u, nn, &dt[A->keys[b].sim], unew, ff, A->cnt);
-        for (int z = 0; z < G->n[2]; z++)
-            for (int y = 0; y < G->n[1]; y++)
-                for (int x = 0; x < G->n[0]; x++)
-                    for (int k = 0; k < A->nv; k++)
-                        u[k * G->P + at(G, x, y, z)] = unew[k * G->I + interior_index(G, x, y, z)];
+    /* every block reads only its own padded tile, so blocks are independent */
+#pragma omp parallel num_threads(g_threads)
+    {
+        double *unew = malloc(sizeof(double) * A->nv * G->I);
+#pragma omp for schedule(dynamic, 4)
+        for (int b = 0; b < A->nb; b++) {
+            if (A->haskids[b])
+                continue;
+            double dx[3];
+            block_dx(A, b, dx);
+            double *u = tile(A, b);
+            double *ff = A->ff + (size_t)b * 2 * A->nd * A->nv * A->T;
+            long cnt[4] = {0, 0, 0, 0};
+            orc_step_tile(&A->p, dx, u, nn, &dt[A->keys[b].sim], unew, ff, cnt);
+            add_counters(A, cnt);
+            for (int z = 0; z < G->n[2]; z++)
+                for (int y = 0; y < G->n[1]; y++)
+                    for (int x = 0; x < G->n[0]; x++)
+                        for (int k = 0; k < A->nv; k++)
+                            u[k * G->P + at(G, x, y, z)] = unew[k * G->I + interior_index(G, x, y, z)];
+        }
+        free(unew);
     }
-    free(unew);
 }
 
 /* WENO with TVD Runge-Kutta 2 on the tree: stage 1 on every leaf into a
@@ -1536,21 +1609,28 @@ static void amr_weno_rk2(orc_amr *A, const orc_dtrec *dt)
     size_t nff = (size_t)A->nb * 2 * A->nd * nv * A->T;
     double *U1 = malloc(sizeof(double) * ntot);
     double *ff1 = calloc(nff, sizeof(double));
-    double *unew = malloc(sizeof(double) * nv * G->I);
     memcpy(U1, A->U, sizeof(double) * ntot);
-    for (int b = 0; b < A->nb; b++) {
-        if (A->haskids[b])
-            continue;
-        double dx[3];
-        block_dx(A, b, dx);
-        orc_step_tile(&A->p, dx, tile(A, b), nn, &dt[A->keys[b].sim], unew,
-                      ff1 + (size_t)b * 2 * A->nd * nv * A->T, A->cnt);
-        double *u1 = U1 + (size_t)b * nv * G->P;
-        for (int z = 0; z < G->n[2]; z++)
-            for (int y = 0; y < G->n[1]; y++)
-                for (int x = 0; x < G->n[0]; x++)
-                    for (int k = 0; k < nv; k++)
-                        u1[k * G->P + at(G, x, y, z)] = unew[k * G->I + interior_index(G, x, y, z)];
+#pragma omp parallel num_threads(g_threads)
+    {
+        double *unew = malloc(sizeof(double) * nv * G->I);
+#pragma omp for schedule(dynamic, 4)
+        for (int b = 0; b < A->nb; b++) {
+            if (A->haskids[b])
+                continue;
+            double dx[3];
+            block_dx(A, b, dx);
+            long cnt[4] = {0, 0, 0, 0};
+            orc_step_tile(&A->p, dx, tile(A, b), nn, &dt[A->keys[b].sim], unew,
+                          ff1 + (size_t)b * 2 * A->nd * nv * A->T, cnt);
+            add_counters(A, cnt);
+            double *u1 = U1 + (size_t)b * nv * G->P;
+            for (int z = 0; z < G->n[2]; z++)
+                for (int y = 0; y < G->n[1]; y++)
+                    for (int x = 0; x < G->n[0]; x++)
+                        for (int k = 0; k < nv; k++)
+                            u1[k * G->P + at(G, x, y, z)] = unew[k * G->I + interior_index(G, x, y, z)];
+        }
+        free(unew);
     }
     /* the boundary procedure on the stage state */
     double *U0 = A->U;
@@ -1558,31 +1638,38 @@ static void amr_weno_rk2(orc_amr *A, const orc_dtrec *dt)
     orc_amr_restrict(A);
     orc_amr_fill(A);
     A->U = U0;
-    for (int b = 0; b < A->nb; b++) {
-        if (A->haskids[b])
-            continue;
-        double dx[3];
-        block_dx(A, b, dx);
-        const orc_dtrec *r = &dt[A->keys[b].sim];
-        double *ff = A->ff + (size_t)b * 2 * A->nd * nv * A->T;
-        orc_step_tile(&A->p, dx, U1 + (size_t)b * nv * G->P, nn, r, unew, ff, A->cnt);
-        double *u = tile(A, b);
-        for (int z = 0; z < G->n[2]; z++)
-            for (int y = 0; y < G->n[1]; y++)
-                for (int x = 0; x < G->n[0]; x++) {
-                    long c = at(G, x, y, z), ic = interior_index(G, x, y, z);
-                    for (int k = 0; k < nv; k++)
-                        u[k * G->P + c] = 0.5 * (u[k * G->P + c] + unew[k * G->I + ic]);
-                    if (A->p.physics == ORC_MHD)
-                        u[PSI * G->P + c] = u[PSI * G->P + c] * r->damp;
-                }
-        const double *f1 = ff1 + (size_t)b * 2 * A->nd * nv * A->T;
-        for (size_t i = 0; i < (size_t)2 * A->nd * nv * A->T; i++)
-            ff[i] = 0.5 * f1[i] + 0.5 * ff[i];
+#pragma omp parallel num_threads(g_threads)
+    {
+        double *unew = malloc(sizeof(double) * nv * G->I);
+#pragma omp for schedule(dynamic, 4)
+        for (int b = 0; b < A->nb; b++) {
+            if (A->haskids[b])
+                continue;
+            double dx[3];
+            block_dx(A, b, dx);
+            const orc_dtrec *r = &dt[A->keys[b].sim];
+            double *ff = A->ff + (size_t)b * 2 * A->nd * nv * A->T;
+            long cnt[4] = {0, 0, 0, 0};
+            orc_step_tile(&A->p, dx, U1 + (size_t)b * nv * G->P, nn, r, unew, ff, cnt);
+            add_counters(A, cnt);
+            double *u = tile(A, b);
+            for (int z = 0; z < G->n[2]; z++)
+                for (int y = 0; y < G->n[1]; y++)
+                    for (int x = 0; x < G->n[0]; x++) {
+                        long c = at(G, x, y, z), ic = interior_index(G, x, y, z);
+                        for (int k = 0; k < nv; k++)
+                            u[k * G->P + c] = 0.5 * (u[k * G->P + c] + unew[k * G->I + ic]);
+                        if (A->p.physics == ORC_MHD)
+                            u[PSI * G->P + c] = u[PSI * G->P + c] * r->damp;
+                    }
+            const double *f1 = ff1 + (size_t)b * 2 * A->nd * nv * A->T;
+            for (size_t i = 0; i < (size_t)2 * A->nd * nv * A->T; i++)
+                ff[i] = 0.5 * f1[i] + 0.5 * ff[i];
+        }
+        free(unew);
     }
     free(U1);
     free(ff1);
-    free(unew);
 }
 
 /* Sec. 4.3 step 2: a coarse leaf next to finer leaves replaces its own face
@@ -1592,6 +1679,8 @@ void orc_amr_reflux(orc_amr *A, const orc_dtrec *dt)
     geo *G = &A->G;
     int n = A->n, nd = A->nd, nv = A->nv;
     long T = A->T;
+    /* a coarse leaf writes only its own cells and reads fine face fluxes */
+#pragma omp parallel for schedule(dynamic, 8) num_threads(g_threads)
     for (int b = 0; b < A->nb; b++) {
         if (A->haskids[b])
             continue;
@@ -1715,6 +1804,7 @@ void orc_amr_conduct(orc_amr *A, const orc_dtrec *dt)
             sub[s] = dt[s];
             sub[s].dt = i < dt[s].nsub ? dt[s].dt_sub : 0.0;
         }
+#pragma omp parallel for schedule(dynamic, 4) num_threads(g_threads)
         for (int b = 0; b < A->nb; b++) {
             double *ff = A->ff + (size_t)b * nff;
             if (A->haskids[b])

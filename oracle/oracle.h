@@ -62,6 +62,11 @@ typedef struct {
     int sim, level, ix, iy, iz;
 } orc_key;
 
+/* threads of the block-tree loops (orc_amr_*), default 1; results are the
+ * same bit for bit for any count */
+void   orc_set_threads(int n);
+int    orc_get_threads(void);
+
 /* ---- pointwise physics (Sec. 2, Sec. 3) ---- */
 int    orc_nvar(const orc_params *p);
 double orc_pressure(const orc_params *p, const double *u);
@@ -90,6 +95,13 @@ void   orc_prim_to_cons(const orc_params *p, double *w, long ncell);
 void orc_step_tile(const orc_params *p, const double dx[3], const double *u,
                    const int n[3], const orc_dtrec *dt, double *unew,
                    double *ff, long *cnt);
+/* LF intermediate states (positivity fall-back tests): ut[nvar][P] the
+ * predicted state, sl[ndim][nvar][P] the slopes after the fall-back,
+ * lr[ndim][2][nvar][P] the left/right states each face flux receives
+ * (face c+1/2 at cell c); cnt as in orc_step_tile. */
+void orc_lf_states(const orc_params *p, const double dx[3], const double *u,
+                   const int n[3], const orc_dtrec *dt, double *ut, double *sl,
+                   double *lr, long *cnt);
 /* EGLM source densities -(divB)B and -B.grad(psi) on the interior,
  * out[nvar][interior] (zero for the other components). */
 void orc_eglm_source(const orc_params *p, const double dx[3], const double *u,

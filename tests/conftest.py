@@ -14,6 +14,18 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long CPU test")
 
 
+ORACLE_THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _oracle_threads():
+    """The oracle's block-tree loops run on the host's cores (results are the
+    one-thread results bit for bit)."""
+    import oracle
+    oracle.build(force=False)
+    oracle.set_threads(ORACLE_THREADS)
+
+
 @pytest.fixture(scope="session")
 def orc():
     import oracle

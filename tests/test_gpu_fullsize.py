@@ -1,5 +1,10 @@
 """Full-size checks at the benchmark's shapes and launch configuration.
 
+* The whole 128^3 Harris sheet with 4 levels (22016 blocks, 79.2 M leaf
+  cells), two whole cycles in the benchmark's launch configuration
+  (autotuned, graph-captured) against the oracle run on the host's cores over
+  every leaf: FP64 to 1e-11 relative L-infinity, dt records to 1e-12; FP32
+  (the headline state) in volume-weighted relative L1 per variable.
 * Sampled outputs: one batched step launch (persistent grid picked by the
   autotuner, as in bench.py) on the 128^3 Harris sheet with 4 levels, for
   leaves whose 26 same-level neighbours exist; the oracle steps the same blocks
@@ -34,6 +39,98 @@ def dev():
         pytest.fail("GPU tests need a HIP device")
     N.lib()
     return "cuda:0"
+
+
+# FP32 state against the FP64 oracle after two whole cycles of the full
+# Harris sheet: volume-weighted relative L1 of rho, e and |B| (each FP32
+# rounding of a state of size 1 is 6e-8; two cycles of arithmetic stay
+# within a few of those).
+FP32_L1_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def harris_oracle(orc):
+    """The oracle's two cycles of the full Harris sheet (FP64, all host cores
+    up to 16), with the dt records; the generator's primitive data is formed
+    once and handed to both sides."""
+    import os
+    w = W.harris3d(precision="fp64")
+    leaves = np.nonzero(w.leaf_mask())[0]
+    pos = np.full(len(w.keys), -1, dtype=np.int64)
+    pos[leaves] = np.arange(len(leaves))
+    _say(f"harris 128^3 L4: generator data for {len(leaves)} leaves")
+    prim = w.primitive_blocks(leaves)
+
+    def cached(blocks):
+        return prim[pos[np.asarray(blocks, dtype=np.int64)]]
+
+    before = orc.get_threads()
+    threads = min(16, os.cpu_count() or 1)
+    orc.set_threads(threads)
+    try:
+        w.primitive_blocks = cached
+        _say(f"  oracle load and 2 cycles on {threads} threads")
+        A = orc.load_workload(w)
+        tr = A.run(2, trace=True)
+    finally:
+        orc.set_threads(before)
+    _say("  oracle done")
+    return w, A, tr, cached
+
+
+def _leaf_norms(w, sim, A, chunk=1024):
+    """Over every leaf interior, per variable (9) and |B| (index 9): max |g - o|,
+    max |o|, volume-weighted sum |g - o| and sum |o|."""
+    leaves = np.nonzero(w.leaf_mask())[0]
+    out = np.zeros((4, 10))
+    for s in range(0, len(leaves), chunk):
+        idx = leaves[s:s + chunk]
+        g = sim.state_by_key(idx)[:, :, 2:-2, 2:-2, 2:-2]
+        o = A.state[idx][:, :, 2:-2, 2:-2, 2:-2]
+        vol = np.array([np.prod(w.dx(int(k[0]), int(k[1]))) for k in w.keys[idx]])
+        gb = np.sqrt((g[:, 4:7] ** 2).sum(axis=1))[:, None]
+        ob = np.sqrt((o[:, 4:7] ** 2).sum(axis=1))[:, None]
+        g = np.concatenate([g, gb], axis=1)
+        o = np.concatenate([o, ob], axis=1)
+        d = np.abs(g - o)
+        out[0] = np.maximum(out[0], d.max(axis=(0, 2, 3, 4)))
+        out[1] = np.maximum(out[1], np.abs(o).max(axis=(0, 2, 3, 4)))
+        out[2] += (d.sum(axis=(2, 3, 4)) * vol[:, None]).sum(axis=0)
+        out[3] += (np.abs(o).sum(axis=(2, 3, 4)) * vol[:, None]).sum(axis=0)
+    return out
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_harris_full_size_cycles_vs_oracle(dev, harris_oracle, precision):
+    from paper_1204_5849_amd.sim import Simulation
+    w64, A, tr, cached = harris_oracle
+    w = W.harris3d(precision=precision)
+    w.primitive_blocks = cached
+    _say(f"harris 128^3 L4 {precision}: load, autotune, 2 graph cycles")
+    sim = Simulation(w, precision=precision)
+    sim.load_initial()
+    sim.autotune()
+    sim.graph_run(2)
+    sim.sync()
+    rec = sim.dt.cpu().numpy()[0]
+    st, cnt = sim.flags()
+    assert st == 0 and cnt[2] == 0 and cnt[3] == 0
+    nrm = _leaf_norms(w, sim, A)
+    linf = nrm[0] / np.where(nrm[1] > 0, nrm[1], 1.0)
+    l1 = nrm[2] / np.where(nrm[3] > 0, nrm[3], 1.0)
+    names = ["rho", "mx", "my", "mz", "Bx", "By", "Bz", "e", "psi", "|B|"]
+    _say("  rel Linf " + " ".join(f"{n} {v:.2e}" for n, v in zip(names, linf)))
+    _say("  rel L1   " + " ".join(f"{n} {v:.2e}" for n, v in zip(names, l1)))
+    if precision == "fp64":
+        np.testing.assert_allclose(rec[:4], tr[-1, 0, :4], rtol=1e-12)
+        psi_scale = max(nrm[1][8], tr[-1, 0, 1] * nrm[1][4:7].max())
+        assert np.all(linf[:8] <= 1e-11), linf
+        assert nrm[0][8] / psi_scale <= 1e-11
+    else:
+        np.testing.assert_allclose(rec[:4], tr[-1, 0, :4], rtol=1e-5)
+        assert l1[0] <= FP32_L1_TOL and l1[7] <= FP32_L1_TOL and l1[9] <= FP32_L1_TOL, l1
+    del sim
+    torch.cuda.empty_cache()
 
 
 def _pick_interior_leaves(w, ctx, per_level=3, seed=3):

@@ -64,16 +64,25 @@ def _tree2d(precision):
 @pytest.mark.parametrize("name,precision", [("ot", "fp64"), ("ot", "fp32"), ("blast", "fp64"),
                                             ("harris", "fp32")])
 def test_estimate_matches_oracle(dev, orc, name, precision):
+    """The estimator after two cycles (ghost frames left as the cycle leaves
+    them: the estimate reads in place) against the oracle's estimate of its
+    own state after the same two cycles.  FP64: the states agree to rounding,
+    so the estimates to 1e-10; FP32: the state itself differs from the FP64
+    one by FP32 rounding, relative 1e-4 on estimates above 1e-3."""
     w = _tree2d(precision) if name == "ot" else _workload(name, precision)
     _say(f"estimate {name} {precision}: {len(w.keys)} blocks")
     s = _sim(w)
-    s.advance(2)  # ghost frames are left unspecified by the cycle: the estimate reads in place
+    s.advance(2)
     got = s.estimate(CRIT)
-    s.fill()
-    want = _oracle_err(orc, w, s.state_by_key())
-    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-300)
-    _say(f"  max rel diff {rel.max():.2e}, estimates in [{want.min():.3g}, {want.max():.3g}]")
-    assert rel.max() <= 1e-12
+    A = orc.load_workload(w)
+    A.run(2)
+    want = _oracle_err(orc, w, A.state)
+    big = want > 1e-3
+    rel = np.abs(got - want)[big] / want[big]
+    _say(f"  max rel diff {rel.max():.2e} over {int(big.sum())} blocks, estimates in "
+         f"[{want.min():.3g}, {want.max():.3g}]")
+    assert big.sum() >= len(want) // 2
+    assert rel.max() <= (1e-10 if precision == "fp64" else 1e-4)
 
 
 def _interior(w, U):
@@ -82,14 +91,26 @@ def _interior(w, U):
     return U[:, :, :, 2:-2, 2:-2]
 
 
+def _gap_threshold(vals, lo, hi):
+    """A threshold between two sorted distinct values at positions in
+    [lo, hi) of the sorted list, at the largest relative gap there, so that
+    estimates that differ by rounding fall on the same side of it."""
+    v = np.sort(np.unique(vals))
+    if len(v) < 2:  # all alike: every one of them is above the threshold
+        return v[0] * (1.0 - 1e-6)
+    a = min(max(1, int(lo * len(v))), len(v) - 1)
+    b = min(max(a + 1, int(hi * len(v))), len(v))
+    i = max(range(a, b), key=lambda j: (v[j] - v[j - 1]) / v[j])
+    return 0.5 * (v[i] + v[i - 1])
+
+
 def _thresholds(w, err):
-    """Refine the top fifth of the leaves; destroy the children of the
-    smoother half of the blocks whose children are all leaves.  Thresholds
-    sit at midpoints between sorted estimates, so none is on a threshold."""
+    """Refine about the top fifth of the leaves; destroy the children of
+    about the smoother half of the blocks whose children are all leaves."""
     leaves = w.leaf_mask()
-    le = np.sort(np.unique(err[leaves]))
-    tr = 0.5 * (le[int(0.8 * len(le))] + le[int(0.8 * len(le)) - 1])
+    tr = _gap_threshold(err[leaves], 0.7, 0.9)
     keyset = {tuple(int(v) for v in k) for k in w.keys}
+    kid_parents = {(s2, l2 - 1, x2 >> 1, y2 >> 1, z2 >> 1) for (s2, l2, x2, y2, z2) in keyset}
     cand = []
     for i, k in enumerate(w.keys):
         if leaves[i]:
@@ -97,14 +118,12 @@ def _thresholds(w, err):
         s, lv, x, y, z = (int(v) for v in k)
         kids = [(s, lv + 1, 2 * x + (c & 1), 2 * y + ((c >> 1) & 1),
                  2 * z + ((c >> 2) & 1) if w.ndim == 3 else 0) for c in range(1 << w.ndim)]
-        kid_parents = {(s2, l2 - 1, x2 >> 1, y2 >> 1, z2 >> 1) for (s2, l2, x2, y2, z2) in keyset}
         if all(c in keyset and c not in kid_parents for c in kids):
             cand.append(err[i])
-    pe = np.sort(np.unique(cand))
-    if len(pe) > 1:
-        tc = 0.5 * (pe[len(pe) // 2] + pe[len(pe) // 2 - 1])
+    if len(np.unique(cand)) > 1:
+        tc = _gap_threshold(cand, 0.3, 0.7)
     else:  # all candidates alike (a symmetric problem): all of them qualify
-        tc = pe[0] * (1.0 + 1e-6) + 1e-300
+        tc = max(cand) * (1.0 + 1e-6) + 1e-300
     return tr, tc
 
 
@@ -133,43 +152,62 @@ def _oracle_remap(orc, w_new, w_old, old_full):
     return B, new_blocks
 
 
-@pytest.mark.parametrize("name", ["ot", "blast"])
-def test_remap_matches_oracle(dev, orc, name):
+@pytest.mark.parametrize("name,cycles", [("ot", 0), ("blast", 2)])
+def test_remap_matches_oracle(dev, orc, name, cycles):
+    """One regrid, decided and carried out by each side on its own state:
+    the oracle forms its estimates, thresholds and new tree (oracle.regrid)
+    and moves its state (copies, prolongation, restriction, fill); the
+    library's estimate, tree edit with the same thresholds and remap must
+    give the same tree and the same state: bit for bit from the initial
+    data (Orszag-Tang), to 1e-11 after two cycles (the blast, whose initial
+    density and field are uniform, so that every estimate is zero)."""
     # 3-D: a 4^3 base, so that smooth blocks can lose their children without
     # touching the new finest blocks (on a 2^3 periodic base every block
     # touches every other)
     w = _tree2d("fp64") if name == "ot" else W.blast3d(nbase=4, levels=2, precision="fp64")
+    A = orc.load_workload(w)
+    A.run(cycles)
+    err_o = _oracle_err(orc, w, A.state)
+    tr, tc = _thresholds(w, err_o)
+    want_keys = oracle_regrid([tuple(int(v) for v in k) for k in w.keys], w.sims, w.ndim,
+                              {tuple(int(v) for v in k): e for k, e in zip(w.keys, err_o)},
+                              tr, tc, 3)
     s = _sim(w)
-    s.advance(2)
-    err = s.estimate(CRIT)
-    tr, tc = _thresholds(w, err)
+    s.advance(cycles)
     new = s.regrid(CRIT, tr, tc, 3)
-    want_keys = oracle_regrid([tuple(k) for k in w.keys], w.sims, w.ndim,
-                              {tuple(int(v) for v in k): e for k, e in zip(w.keys, err)}, tr, tc, 3)
     assert [tuple(int(v) for v in k) for k in new.wl.keys] == want_keys
-    s.fill()
-    B, new_blocks = _oracle_remap(orc, new.wl, w, s.state_by_key())
+    B, new_blocks = _oracle_remap(orc, new.wl, w, A.state)
     created, destroyed = _changes(w, new.wl)
     _say(f"remap {name}: {len(w.keys)} -> {len(new.wl.keys)} blocks, {created} created, "
          f"{destroyed} destroyed (tau_refine {tr:.3g}, tau_coarsen {tc:.3g})")
     assert created == len(new_blocks) and created > 0 and destroyed > 0
-    assert np.array_equal(new.state_by_key(), B.state)
+    got = new.state_by_key()
+    if cycles == 0:
+        assert np.array_equal(got, B.state)
+    else:
+        err = rel_linf(_interior(new.wl, got), _interior(new.wl, B.state))
+        _say(f"  rel Linf per var {np.array2string(err, precision=2)}")
+        assert np.all(err[:8] <= 1e-11)
 
 
 @pytest.mark.parametrize("name", ["ot", "blast"])
 def test_regrid_then_cycles_match_oracle(dev, orc, name):
-    """Cycles, a regrid that refines and coarsens, more cycles: the leaves
-    agree with the oracle doing the same (FP64)."""
+    """Cycles, a regrid that refines and coarsens, more cycles, each side on
+    its own state: the oracle's estimates decide the thresholds and its own
+    tree, which the library's tree edit must reproduce; the leaves then agree
+    with the oracle (FP64)."""
     w = _tree2d("fp64") if name == "ot" else _workload(name, "fp64")
     s = _sim(w)
     A = orc.load_workload(w)
     s.advance(3)
     A.run(3)
-    err = s.estimate(CRIT)
-    tr, tc = _thresholds(w, err)
+    err_o = _oracle_err(orc, w, A.state)
+    tr, tc = _thresholds(w, err_o)
+    want_keys = oracle_regrid([tuple(int(v) for v in k) for k in w.keys], w.sims, w.ndim,
+                              {tuple(int(v) for v in k): e for k, e in zip(w.keys, err_o)},
+                              tr, tc, 3)
     new = s.regrid(CRIT, tr, tc, 3)
-    s.fill()
-    # the oracle starts from its own state
+    assert [tuple(int(v) for v in k) for k in new.wl.keys] == want_keys
     B, _ = _oracle_remap(orc, new.wl, w, A.state)
     new.advance(4)
     B.run(4)
@@ -180,4 +218,5 @@ def test_regrid_then_cycles_match_oracle(dev, orc, name):
     created, destroyed = _changes(w, new.wl)
     _say(f"{name} regrid ({created} created, {destroyed} destroyed) + 4 cycles: "
          f"rel Linf per var {np.array2string(err8, precision=2)}")
+    assert created > 0
     assert np.all(err8[:8] <= 1e-11)

@@ -190,3 +190,44 @@ def test_restrict_preserves_volume_integral(orc, rng):
     A.state[:] = uni
     A.restrict()
     assert np.array_equal(A.state, uni)
+
+
+def _threaded_run(orc, w, threads, nsteps):
+    before = orc.get_threads()
+    orc.set_threads(threads)
+    try:
+        A = orc.load_workload(w)
+        tr = A.run(nsteps, trace=True)
+        return A.state.copy(), tr, A.counters()
+    finally:
+        orc.set_threads(before)
+
+
+@pytest.mark.parametrize("ndim,scheme,cond", [(2, "lf", "off"), (2, "mmc", "off"),
+                                             (3, "lf", "off"), (3, "weno", "off"),
+                                             (3, "lf", "field")])
+def test_threads_give_the_one_thread_result_bitwise(orc, ndim, scheme, cond):
+    """The block loops of the tree (fill, restriction, CFL, step, reflux,
+    conduction) run on several threads; state, dt records and counters
+    equal the one-thread run bit for bit."""
+    rng = np.random.default_rng(77 + ndim)
+    nb = (3, 2, 1) if ndim == 2 else (2, 2, 2)
+    bcs = (("periodic", "periodic"), ("outflow", "outflow"), ("periodic", "periodic"))
+    sims = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=nb, bc=bcs)]
+    keys = random_tree(sims, ndim, 3, 0.35, rng)
+
+    def ic(wl, sim, lv, x, y, z, g):
+        tp = 2 * np.pi
+        return [1.0 + 0.3 * np.sin(tp * x) * np.cos(tp * y), 0.4 * np.sin(tp * y),
+                0.3 * np.sin(tp * (x + z)), 0.1 * np.cos(tp * z), 0.5 + 0.2 * np.cos(tp * y),
+                0.3 * np.sin(tp * x), 0.2 + 0.1 * np.sin(tp * z), 1.0 + 0.2 * np.cos(tp * x),
+                0.05 * np.sin(tp * y)]
+
+    w = W.Workload(name="tree", ndim=ndim, sims=sims, keys=keys, ic=ic, scheme=scheme,
+                   limiter="vanleer" if scheme == "mmc" else "minmod", eta=1e-3 if ndim == 3 else 0.0,
+                   cond=cond, kappa0=0.05 if cond != "off" else 0.0)
+    s1, t1, c1 = _threaded_run(orc, w, 1, 3)
+    s8, t8, c8 = _threaded_run(orc, w, 8, 3)
+    assert np.array_equal(t1, t8)
+    assert np.array_equal(c1, c8)
+    assert np.array_equal(s1, s8)

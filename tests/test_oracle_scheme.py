@@ -253,3 +253,92 @@ def test_lf_positivity_fallback_keeps_state_admissible(orc):
     u1, _, cnt = orc.step_tile(p, (1 / N, 1 / N), tile, n, rec)
     assert np.all(np.isfinite(u1))
     assert cnt[0] + cnt[1] > 0
+
+
+# ---------------------------------------------------------------- positivity fall-back
+# Hand-computed pins of the reading of Sec. 3.2 (the slopes of limiter1 and the
+# face states of limiter2): a cell any of whose 2d limited face states has
+# rho <= 0 or p <= 0 takes zero slopes in EVERY dimension for the step; a
+# corrector face state with rho <= 0 or p <= 0 is replaced by the predicted
+# state u~ of its own cell (not by u^n).  Every number below is worked out by
+# hand in the comments and is exact in binary.
+
+def _cons_tile(orc, p, n):
+    """Padded tile of rho = 1, m = 0, B = 0, psi = 0 (conserved variables)."""
+    t = np.zeros(orc.tile_shape(p, n))
+    t[0] = 1.0
+    return t
+
+
+def test_lf_fallback_zeroes_every_slope_of_the_cell(orc):
+    """2-D tile of 5 x 5 cells, gamma = 5/3.  Background rho = 1, m = 0,
+    e = 1/4.  Row y = 2: m_x = 0 | 1 | 2 and e = 1/4 | 3/4 | 9/4 left of,
+    at and right of the cell c = (2, 2) (e = m^2/2 + 1/4, so p = 1/6 in each
+    cell), and rho = 1/2 below c, 3/2 above it.
+
+    Limited slopes of c (minmod): x: dm = min(1, 1) = 1, de = min(1/2, 3/2)
+    = 1/2; y: drho = min(1/2, 1/2) = 1/2, every other slope 0.  Its right
+    x face state (rho 1, m 3/2, e 1) has e - m^2/(2 rho) = -1/8 < 0, so the
+    cell falls back.  Every other cell's slopes are 0 (each sits next to a
+    flat side).  With all slopes 0 the predictor moves nothing: u~ = u
+    exactly.  Resetting only the x slopes would leave drho_y = 1/2, whose
+    pressure difference moves m_y; not resetting at all moves rho, m_x, e."""
+    p = orc.make_params(ndim=2, gamma=5.0 / 3.0, eglm_sources=False)
+    n = (5, 5, 1)
+    u = _cons_tile(orc, p, n)
+    u[7] = 0.25
+    Y, X = 2 + 2, 2 + 2                       # padded indices of c
+    u[1, 0, Y, :X] = 0.0
+    u[1, 0, Y, X] = 1.0
+    u[1, 0, Y, X + 1:] = 2.0
+    u[7, 0, Y, :X] = 0.25
+    u[7, 0, Y, X] = 0.75
+    u[7, 0, Y, X + 1:] = 2.25
+    u[0, 0, Y - 1, X] = 0.5
+    u[0, 0, Y + 1, X] = 1.5
+    assert all(orc.pressure(p, u[:, 0, j, i]) > 0 for j in range(9) for i in range(9))
+    rec = orc.make_dtrec(0.01, ch=0.0, damp=1.0, alpha=3.0)
+    ut, sl, lr, cnt = orc.lf_states(p, (0.1, 0.1), u, n, rec)
+    assert cnt[0] == 1 and cnt[1] == 0
+    assert np.all(sl[:, :, 0, Y, X] == 0.0)
+    assert np.all(sl == 0.0)
+    # u~ = u on the predictor's region (the interior and one ring)
+    np.testing.assert_array_equal(ut[:, :, 1:-1, 1:-1], u[:, :, 1:-1, 1:-1])
+    # so every face flux receives the cells' own states
+    np.testing.assert_array_equal(lr[0, 0, :, 0, Y, X], u[:, 0, Y, X])
+    np.testing.assert_array_equal(lr[0, 1, :, 0, Y, X - 1], u[:, 0, Y, X])
+    np.testing.assert_array_equal(lr[1, 0, :, 0, Y, X], u[:, 0, Y, X])
+
+
+def test_lf_fallback_face_state_is_the_predicted_state(orc):
+    """A row of 5 cells (2-D tile one cell high), gamma = 3/2, dt/dx = 1/4.
+    rho = 1; m_x = -2 | 0 | 2 and e = 3 | 3/4 | 3 left of, at and right of
+    the cell c = 2 (p = 1/2, 3/8, 1/2).
+
+    Slopes of c: dm = min(2, 2) = 2, de = minmod(-9/4, 9/4) = 0; the
+    neighbours' slopes are 0.  Predictor face states of c: m = +-1, e = 3/4,
+    p = (3/4 - 1/2)/2 = 1/8 > 0, so no slope fall-back.  Their fluxes:
+    rho: +-1; m: 1 + 1/8 on both sides; e: +-(3/4 + 1/8) = +-7/8.  So
+    u~_c = (1 - (1/8)(2), 0, ..., 3/4 - (1/8)(7/4), 0) = (3/4, 0, ..., 17/32, 0).
+    Corrector states of c: u~_c +- (0, 1, 0...) have e - m^2/(2 rho) =
+    17/32 - 2/3 < 0, so both the left state of face c+1/2 and the right state
+    of face c-1/2 become u~_c = (3/4, 0, 0, 0, 0, 0, 0, 17/32, 0); u^n_c
+    would be (1, 0, ..., 3/4, 0).  The other states are the neighbours' u^n."""
+    p = orc.make_params(ndim=2, gamma=1.5, eglm_sources=False)
+    n = (5, 1, 1)
+    u = _cons_tile(orc, p, n)
+    X = 2 + 2
+    u[1, 0, :, :X] = -2.0
+    u[1, 0, :, X + 1:] = 2.0
+    u[7] = 3.0
+    u[7, 0, :, X] = 0.75
+    rec = orc.make_dtrec(0.25, ch=0.0, damp=1.0, alpha=4.0)
+    ut, sl, lr, cnt = orc.lf_states(p, (1.0, 1.0), u, n, rec)
+    assert cnt[0] == 0 and cnt[1] == 2
+    assert sl[0, 1, 0, 2, X] == 2.0 and np.count_nonzero(sl) == 3  # rows y = -1, 0, 1
+    want_ut = np.array([0.75, 0, 0, 0, 0, 0, 0, 17.0 / 32.0, 0])
+    np.testing.assert_array_equal(ut[:, 0, 2, X], want_ut)
+    np.testing.assert_array_equal(lr[0, 0, :, 0, 2, X], want_ut)       # left state of c+1/2
+    np.testing.assert_array_equal(lr[0, 1, :, 0, 2, X], u[:, 0, 2, X + 1])
+    np.testing.assert_array_equal(lr[0, 1, :, 0, 2, X - 1], want_ut)   # right state of c-1/2
+    np.testing.assert_array_equal(lr[0, 0, :, 0, 2, X - 1], u[:, 0, 2, X - 1])
