@@ -139,7 +139,9 @@ map_status map_init_blocks(map_ctx **ctx, const map_params *params, int nsims,
                            const map_block_key *keys);
 
 /* Sizes and the Morton slot of each input key (slot_of_key[nblocks], may be
- * NULL).  Host only. */
+ * NULL): the blocks in the space-filling-curve order of Sec. 4.1 (Morton
+ * here; the paper names Morton and Hilbert orders as equivalent), the
+ * numbering of the block list of Table 1.  Host only. */
 map_status map_query(const map_ctx *ctx, map_sizes *sizes, int32_t *slot_of_key);
 
 /* Ghost source of every (input key, direction) -- the paper's neighbour
@@ -230,32 +232,38 @@ map_status map_conduct(map_ctx *ctx, void *U, const map_dt *dt_dev, void *stream
  * each simulation, totals_dev[nsims][9] (device), fixed reduction order. */
 map_status map_totals(map_ctx *ctx, const void *U, double *totals_dev, void *stream);
 
-/* Counters latched by the kernels since the last call, then cleared:
+/* Counters latched by the kernels since the last call, then cleared (the
+ * paper's check of the solution inside the main loop, Fig. 1, and the
+ * positivity fall-backs of Sec. 3.2):
  * [0] LF cells whose slopes fell back to zero, [1] face states replaced by
  * the cell average, [2] non-positive rho or p seen by the CFL pass,
  * [3] non-finite values seen by the CFL pass.  Synchronises `stream`.
  * Returns MAP_ENONFINITE or MAP_ENEGPRESSURE if [3] or [2] is non-zero. */
 map_status map_status_flags(map_ctx *ctx, uint64_t counters[4], void *stream);
 
-/* nsteps full cycles: cfl_dt, step, reflux, restrict, then the ghosts the
- * next step reads from a block's own tile (copies into the frames of the
- * parents that feed prolongation, prolongation level by level), then the
- * conduction subcycle when params.cond_mode is on (map_conduct), with dt
- * kept on the device (the record of the last step is copied to dt_dev if it
- * is not NULL).  Without conduction, every cycle after the first of a call
- * takes its dt from the cycle before: that cycle's restriction also forms
- * the CFL maxima of the leaves with a parent (their values are final after
- * reflux), a small pass those of the leaves without one; the records equal
- * those map_cfl_dt would form from the state at the start of the cycle.  LF and MMC cycles alternate between U and the workspace's
- * shadow state, and an odd nsteps ends with one device copy back into U;
- * WENO cycles update U in place (the shadow holds the stage).  On return U
- * holds the interiors of every block and its prolongated ghosts; the
- * same-level ghost regions of leaves and of parents hold unspecified values
- * (map_fill_ghosts refreshes them).  Eager launches on `stream`. */
+/* nsteps full cycles of the main loop of Fig. 1 (one global time step,
+ * Sec. 3.7; the boundary procedure of Sec. 4.3 after the update instead of
+ * before it, which is the same cycle shifted): cfl_dt, step, reflux,
+ * restrict, then the ghosts the next step reads from a block's own tile
+ * (copies into the frames of the parents that feed prolongation,
+ * prolongation level by level), then the conduction subcycle when
+ * params.cond_mode is on (map_conduct), with dt kept on the device (the
+ * record of the last step is copied to dt_dev if it is not NULL).  Without
+ * conduction, every cycle after the first of a call takes its dt from the
+ * cycle before: that cycle's restriction also forms the CFL maxima of the
+ * leaves with a parent (their values are final after reflux), a small pass
+ * those of the leaves without one; the records equal those map_cfl_dt
+ * would form from the state at the start of the cycle.  LF and MMC cycles
+ * alternate between U and the workspace's shadow state, and an odd nsteps
+ * ends with one device copy back into U; WENO cycles update U in place (the
+ * shadow holds the stage).  On return U holds the interiors of every block
+ * and its prolongated ghosts; the same-level ghost regions of leaves and of
+ * parents hold unspecified values (map_fill_ghosts refreshes them).  Eager
+ * launches on `stream`. */
 map_status map_advance(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void *stream);
 
-/* Same cycles and result as map_advance: the pair of cycles U -> shadow ->
- * U (WENO: two in-place cycles) is captured once per U into a HIP graph and
+/* Same cycles (Fig. 1) and result as map_advance: the pair of cycles
+ * U -> shadow -> U (WENO: two in-place cycles) is captured once per U into a HIP graph and
  * replayed nsteps / 2 times on `stream` (without conduction, two captures:
  * the first pair of a call forms its first dt, the later ones start from
  * the dt the pair before formed); an odd nsteps adds one eager cycle (and

@@ -67,8 +67,9 @@ def test_estimate_matches_oracle(dev, orc, name, precision):
     """The estimator after two cycles (ghost frames left as the cycle leaves
     them: the estimate reads in place) against the oracle's estimate of its
     own state after the same two cycles.  FP64: the states agree to rounding,
-    so the estimates to 1e-10; FP32: the state itself differs from the FP64
-    one by FP32 rounding, relative 1e-4 on estimates above 1e-3."""
+    so the estimates to 1e-10 relative (1e-13 absolute below 1e-3, where
+    smooth blocks estimate 0); FP32: the state itself differs from the FP64
+    one by FP32 rounding, 1e-4 relative (1e-6 absolute)."""
     w = _tree2d(precision) if name == "ot" else _workload(name, precision)
     _say(f"estimate {name} {precision}: {len(w.keys)} blocks")
     s = _sim(w)
@@ -79,10 +80,12 @@ def test_estimate_matches_oracle(dev, orc, name, precision):
     want = _oracle_err(orc, w, A.state)
     big = want > 1e-3
     rel = np.abs(got - want)[big] / want[big]
-    _say(f"  max rel diff {rel.max():.2e} over {int(big.sum())} blocks, estimates in "
-         f"[{want.min():.3g}, {want.max():.3g}]")
-    assert big.sum() >= len(want) // 2
+    small = np.abs(got - want)[~big].max() if (~big).any() else 0.0
+    _say(f"  max rel diff {rel.max():.2e} over {int(big.sum())} blocks, max abs diff "
+         f"{small:.2e} over the others, estimates in [{want.min():.3g}, {want.max():.3g}]")
+    assert big.sum() >= 8
     assert rel.max() <= (1e-10 if precision == "fp64" else 1e-4)
+    assert small <= (1e-13 if precision == "fp64" else 1e-6)
 
 
 def _interior(w, U):
