@@ -232,6 +232,22 @@ map_status map_conduct(map_ctx *ctx, void *U, const map_dt *dt_dev, void *stream
  * each simulation, totals_dev[nsims][9] (device), fixed reduction order. */
 map_status map_totals(map_ctx *ctx, const void *U, double *totals_dev, void *stream);
 
+/* For callers that cannot allocate device memory or bind scratch (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the result of map_totals, with the per-leaf partial sums in a fixed
+ * library-owned device array instead of the workspace.  The array holds
+ * MAP_STATIC_SCRATCH_DOUBLES doubles (4 MiB) per GPU, is held by every GPU
+ * the library runs on until the process ends, and is shared by all calls
+ * on that GPU: calls that overlap in time on one GPU (two streams, or two
+ * threads) race and give undefined totals.  Nothing is allocated or freed;
+ * every scratch entry a call reads is written earlier in the same call, so
+ * no clearing is needed.  Needs a bound context (the tables stay in the
+ * workspace).  Errors: MAP_EINVAL when nleaves x 9 exceeds the scratch
+ * (more than MAP_STATIC_SCRATCH_DOUBLES / 9 = 58254 leaves) -- checked
+ * before anything else, from the host -- and as map_totals. */
+#define MAP_STATIC_SCRATCH_DOUBLES 524288
+map_status map_totals_static(map_ctx *ctx, const void *U, double *totals_dev, void *stream);
+
 /* Counters latched by the kernels since the last call, then cleared (the
  * paper's check of the solution inside the main loop, Fig. 1, and the
  * positivity fall-backs of Sec. 3.2):

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -49,6 +50,36 @@ map_status need_bound(map_ctx *c)
 }
 
 hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- fixed device scratch of map_totals_static --------------------------
+// The per-leaf partial sums of the totals for callers that cannot allocate
+// (graph capture, serving loops): one array per GPU, held until the process
+// ends, shared by every call on that GPU.  Host code never uses the array's
+// name as an address: the device address of each GPU's copy is taken once,
+// with that GPU current, by hipGetSymbolAddress and kept in g_scratch_ptr.
+constexpr int MAX_DEVICES = 64;
+static __device__ __align__(256) double scratch[MAP_STATIC_SCRATCH_DOUBLES];
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// the current device's scratch address, taken on first use on that device
+map_status scratch_of_current_device(double **out)
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(MAP_EINVAL, "device index " + std::to_string(dev) + " out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr)
+            return fail(MAP_EHIP, "hipGetSymbolAddress returned a null scratch address");
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return MAP_OK;
+}
 
 bool fp64(const map_ctx *c) { return c->p.precision == MAP_FP64; }
 
@@ -553,6 +584,13 @@ map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
     // the host vectors above are pageable: finish the copies before returning
     HIPCHK(hipStreamSynchronize(s));
     c->last_dt = c->ws.dt;
+    {
+        // the static scratch's address on this device, once per device
+        double *sp = nullptr;
+        map_status sst = scratch_of_current_device(&sp);
+        if (sst != MAP_OK)
+            return sst;
+    }
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
@@ -664,6 +702,25 @@ map_status map_conduct(map_ctx *c, void *U, const map_dt *dt_dev, void *stream)
     return run_conduct(c, U, shadow(c), dt_dev, S(stream));
 }
 
+// totals of the leaves with the per-leaf partial sums in `part`
+// (nleaves x NV doubles, every entry written before it is read)
+map_status run_totals(map_ctx *c, const void *U, double *totals_dev, double *part, hipStream_t s)
+{
+    TotalsArgs a{};
+    a.U = U;
+    a.leaves = dptr<int32_t>(c, c->ws.leaves);
+    a.nleaves = c->nleaves;
+    a.blk = dptr<BlockRec>(c, c->ws.blocks);
+    a.lvl_dx = dptr<double>(c, c->ws.lvl_dx);
+    a.part = part;
+    a.sims = dptr<SimRec>(c, c->ws.sims);
+    a.out = totals_dev;
+    a.nsims = (int)c->sims.size();
+    a.ndim = c->nd;
+    HIPCHK(launch_totals(c->nd, fp64(c), a, s));
+    return MAP_OK;
+}
+
 map_status map_totals(map_ctx *c, const void *U, double *totals_dev, void *stream)
 {
     map_status st = need_bound(c);
@@ -671,19 +728,29 @@ map_status map_totals(map_ctx *c, const void *U, double *totals_dev, void *strea
         return st;
     if (!U || !totals_dev)
         return fail(MAP_EINVAL, "null U or output");
-    TotalsArgs a{};
-    a.U = U;
-    a.leaves = dptr<int32_t>(c, c->ws.leaves);
-    a.nleaves = c->nleaves;
-    a.blk = dptr<BlockRec>(c, c->ws.blocks);
-    a.lvl_dx = dptr<double>(c, c->ws.lvl_dx);
-    a.part = dptr<double>(c, c->ws.tot_part);
-    a.sims = dptr<SimRec>(c, c->ws.sims);
-    a.out = totals_dev;
-    a.nsims = (int)c->sims.size();
-    a.ndim = c->nd;
-    HIPCHK(launch_totals(c->nd, fp64(c), a, S(stream)));
-    return MAP_OK;
+    return run_totals(c, U, totals_dev, dptr<double>(c, c->ws.tot_part), S(stream));
+}
+
+map_status map_totals_static(map_ctx *c, const void *U, double *totals_dev, void *stream)
+{
+    if (!c)
+        return fail(MAP_EINVAL, "null context");
+    const size_t need = (size_t)c->nleaves * NV;
+    if (need > (size_t)MAP_STATIC_SCRATCH_DOUBLES)
+        return fail(MAP_EINVAL, std::to_string(c->nleaves) + " leaves need " +
+                                    std::to_string(need) + " doubles of scratch; the static "
+                                    "scratch holds " + std::to_string(MAP_STATIC_SCRATCH_DOUBLES) +
+                                    " (" + std::to_string(MAP_STATIC_SCRATCH_DOUBLES / NV) +
+                                    " leaves)");
+    map_status st = need_bound(c);
+    if (st)
+        return st;
+    if (!U || !totals_dev)
+        return fail(MAP_EINVAL, "null U or output");
+    double *part = nullptr;
+    if ((st = scratch_of_current_device(&part)) != MAP_OK)
+        return st;
+    return run_totals(c, U, totals_dev, part, S(stream));
 }
 
 map_status map_status_flags(map_ctx *c, uint64_t counters[4], void *stream)

@@ -33,7 +33,8 @@ COND = {"off": MAP_COND_OFF, "iso": MAP_COND_ISO, "field": MAP_COND_FIELD}
 
 EXPORTS = ["map_init_blocks", "map_query", "map_neighbors", "map_fill_selection", "map_bind_workspace",
            "map_prim_to_cons", "map_fill_ghosts", "map_restrict", "map_prolong", "map_cfl_dt",
-           "map_step", "map_reflux", "map_conduct", "map_totals", "map_status_flags", "map_advance",
+           "map_step", "map_reflux", "map_conduct", "map_totals", "map_totals_static",
+           "map_status_flags", "map_advance",
            "map_graph_run", "map_set_launch", "map_autotune", "map_estimate", "map_regrid",
            "map_remap", "map_last_error", "map_destroy"]
 
@@ -118,6 +119,7 @@ def lib():
         L.map_reflux.argtypes = [vp, vp, vp, vp]
         L.map_conduct.argtypes = [vp, vp, vp, vp]
         L.map_totals.argtypes = [vp, vp, vp, vp]
+        L.map_totals_static.argtypes = [vp, vp, vp, vp]
         L.map_status_flags.argtypes = [vp, C.POINTER(C.c_uint64), vp]
         L.map_advance.argtypes = [vp, vp, vp, C.c_int, vp]
         L.map_graph_run.argtypes = [vp, vp, vp, C.c_int, vp]
@@ -268,6 +270,10 @@ def map_conduct(ctx, U, dt_dev, stream):
 
 def map_totals(ctx, U, out_dev, stream):
     check(lib().map_totals(ctx, _p(U), _p(out_dev), _p(stream)))
+
+
+def map_totals_static(ctx, U, out_dev, stream):
+    check(lib().map_totals_static(ctx, _p(U), _p(out_dev), _p(stream)))
 
 
 def map_status_flags(ctx, stream):

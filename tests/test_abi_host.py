@@ -257,3 +257,20 @@ def test_each_step_instance_is_compiled_once():
     assert not (sets[0] & sets[1]), sorted(sets[0] & sets[1])
     # 2 precisions x 2 (resistivity) x (3 LF limiters + 2 WENO stages) x 2 fluxes
     assert len(sets[0] | sets[1]) == 40
+
+
+def test_totals_static_rejects_too_many_leaves():
+    """map_totals_static checks, before touching the device, that the leaves'
+    partial sums fit its fixed scratch (MAP_STATIC_SCRATCH_DOUBLES / 9 =
+    58254 leaves)."""
+    from paper_1204_5849_amd import native as N
+    from paper_1204_5849_amd import workloads as W
+    w = W.orszag_tang(256)  # 65536 leaves
+    ctx = N.map_init_blocks(N.make_params(2), w.sims, w.keys)
+    try:
+        st = N.lib().map_totals_static(ctx, None, None, None)
+        assert st == N.MAP_EINVAL
+        msg = N.lib().map_last_error().decode()
+        assert "static scratch" in msg and "58254" in msg, msg
+    finally:
+        N.map_destroy(ctx)
