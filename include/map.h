@@ -62,7 +62,7 @@ enum { MAP_COND_OFF = 0, MAP_COND_ISO = 1, MAP_COND_FIELD = 2 };
  *                 totals in FP64.
  *   scheme        MAP_LF (TVD-LF: MUSCL-Hancock predictor, Rusanov flux,
  *                 Sec. 3.2), MAP_MMC (modified MacCormack, Sec. 3.1, 2-D
- *                 only) or MAP_WENO (third-order component-wise WENO face
+ *                 and 3-D) or MAP_WENO (third-order component-wise WENO face
  *                 states, Rusanov flux, TVD Runge-Kutta 2 in time with the
  *                 boundary procedure applied to the intermediate stage,
  *                 Sec. 3.3).

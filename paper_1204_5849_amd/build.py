@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmap.so")
 SOURCES = ["plan.cpp", "regrid.cpp", "api.hip", "k_step2.hip", "k_step3.hip", "k_step3_ilp.hip",
-           "k_step_mmc.hip", "k_aux.hip", "k_regrid.hip", "k_cond.hip"]
+           "k_step_mmc.hip", "k_step_mmc3.hip", "k_aux.hip", "k_regrid.hip", "k_cond.hip"]
 # per-source options: LLVM's ILP-first scheduler, measured per kernel on
 # MI355X (FP32): the resistive 3-D LF update (VALU-bound at the 256-register
 # limit) 3 % faster with Rusanov and 6 % with HLLC, the resistive first WENO

@@ -2,8 +2,8 @@
 // 2-D blocks: Lax-Friedrichs flux splitting f+- = (f +- alpha u)/2 with the
 // global alpha (c_h on the GLM pair), predictor u~ from h = f+_i + f-_{i+1},
 // and the flux-limited correction built from g+ and g-, all directions
-// together (Sec. 3.7), followed by the same EGLM sources and psi damping as
-// the LF update.
+// together (Sec. 3.7), followed by the same EGLM sources, resistive terms
+// and psi damping as the LF update.  (3-D blocks: k_step_mmc3.hip.)
 //
 // One workgroup per block (256 threads).  The padded tile of u^n is staged
 // in LDS first, its ghost cells read where the ghost descriptors point (a
@@ -229,6 +229,32 @@ __global__ void __launch_bounds__(NT) k_step_mmc2(StepArgs a)
                 o[MZ] = o[MZ] - dt * (divb * ub[BZ * T2 + c]);
                 o[EN] = o[EN] - dt * bgp;
             }
+            // resistive terms -curl(eta J) and -div((eta J) x B) (Sec. 3.5)
+            // from central differences of u^n; in 2-D the z derivatives vanish
+            if (a.eta > 0.0) {
+                const T eta = (T)a.eta;
+                const T *bx = ub + BX * T2, *by = ub + BY * T2, *bz = ub + BZ * T2;
+                // eta J and the x, y rows of eta (J x B) at padded index e
+                auto ej = [&](int e, T (&r)[5]) {
+                    const T jx = (bz[e + PD] - bz[e - PD]) * i2d[1];
+                    const T jy = -((bz[e + 1] - bz[e - 1]) * i2d[0]);
+                    const T jz = (by[e + 1] - by[e - 1]) * i2d[0] - (bx[e + PD] - bx[e - PD]) * i2d[1];
+                    r[0] = eta * jx;
+                    r[1] = eta * jy;
+                    r[2] = eta * jz;
+                    r[3] = eta * (jz * by[e] - jy * bz[e]);
+                    r[4] = eta * (jx * bz[e] - jz * bx[e]);
+                };
+                T xm[5], xp[5], ym[5], yp[5];
+                ej(c - 1, xm);
+                ej(c + 1, xp);
+                ej(c - PD, ym);
+                ej(c + PD, yp);
+                o[BX] = o[BX] + dt * (-((yp[2] - ym[2]) * i2d[1]));
+                o[BY] = o[BY] + dt * ((xp[2] - xm[2]) * i2d[0]);
+                o[BZ] = o[BZ] + dt * ((yp[0] - ym[0]) * i2d[1] - (xp[1] - xm[1]) * i2d[0]);
+                o[EN] = o[EN] + dt * ((xp[3] - xm[3]) * i2d[0] + (yp[4] - ym[4]) * i2d[1]);
+            }
             o[PSI] = o[PSI] * damp;
 #pragma unroll
             for (int v = 0; v < NV; v++)
@@ -257,8 +283,8 @@ static void launch_mmc_lim(const StepArgs &a, int g, hipStream_t s)
 
 hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double, int grid, hipStream_t s)
 {
-    if (ndim != 2)
-        return hipErrorInvalidValue;
+    if (ndim == 3)
+        return launch_step_mmc3(fp64, a.eta > 0.0, a, grid, s);
     if (a.nitems <= 0)
         return hipSuccess;
     int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;

@@ -168,6 +168,7 @@ hipError_t launch_step3(bool fp64, bool resist, int sch, const StepArgs &a, int 
 hipError_t launch_step3_ilp(int sch, const StepArgs &a, int grid, hipStream_t s);
 hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double alpha_unused, int grid,
                            hipStream_t s);
+hipError_t launch_step_mmc3(bool fp64, bool resist, const StepArgs &a, int grid, hipStream_t s);
 int step_blocks_per_group(int ndim, int scheme);
 hipError_t launch_fill_copy(int ndim, bool fp64, const FillArgs &a, int grid, hipStream_t s);
 int fill_blocks_per_group(int ndim);

@@ -80,10 +80,6 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
         err = "gamma, cfl, eta, glm_cd or glm_cr out of range";
         return MAP_EINVAL;
     }
-    if (p->scheme == MAP_MMC && p->ndim != 2) {
-        err = "the MMC scheme is built for 2-D blocks only";
-        return MAP_EINVAL;
-    }
     if (p->riemann != MAP_RUSANOV && p->riemann != MAP_HLLC) {
         err = "unknown riemann solver";
         return MAP_EINVAL;

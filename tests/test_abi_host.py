@@ -89,7 +89,9 @@ def test_param_errors():
     assert _status(N.make_params(2, scheme="mmc", riemann="hllc"), sims, base) == N.MAP_EINVAL
     assert _status(N.make_params(2, scheme="weno", riemann="hllc"), sims, base) == N.MAP_OK
     sims3 = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=(2, 2, 2), bc=(("periodic",) * 2,) * 3)]
-    assert _status(N.make_params(3, scheme="mmc"), sims3, W.base_keys(0, (2, 2, 2), 3)) == N.MAP_EINVAL
+    assert _status(N.make_params(3, scheme="mmc"), sims3, W.base_keys(0, (2, 2, 2), 3)) == N.MAP_OK
+    assert _status(N.make_params(3, scheme="mmc", riemann="hllc"), sims3,
+                   W.base_keys(0, (2, 2, 2), 3)) == N.MAP_EINVAL
     mixed = [W.SimDesc(lo=(0, 0, 0), hi=(1, 1, 1), nbase=(2, 2, 1),
                        bc=(("periodic", "outflow"),) * 3)]
     assert _status(N.make_params(2), mixed, base) == N.MAP_EINVAL

@@ -69,6 +69,46 @@ def test_mmc_scalar_is_sweby_lax_wendroff(orc, limiter):
     np.testing.assert_allclose(u1, want, rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("scheme", ["mmc", "lf"])
+def test_3d_scalar_along_each_axis(orc, scheme, axis):
+    """A 3-D tile whose data varies along one axis only, advected along that
+    axis: every line is the 1-D textbook scheme (Sweby's limited
+    Lax-Wendroff for MMC, MUSCL-Hancock upwind for LF), so a stride or sign
+    slip in any one dimension of the 3-D code shows."""
+    a, N = 1.1, 24
+    adv = [0.0, 0.0, 0.0]
+    adv[axis] = a
+    p = orc.make_params(ndim=3, physics=orc.SCALAR, scheme=scheme, limiter="minmod", adv=adv)
+    n = [4, 4, 4]
+    n[axis] = N
+    x = np.arange(N)
+    u0 = np.sin(2 * np.pi * x / N) + np.where((x > N // 3) & (x < N // 2), 1.0, 0.0)
+    tile = np.zeros(orc.tile_shape(p, n))
+    shape = [1, 1, 1]
+    shape[2 - axis] = N
+    sl = [slice(2, -2)] * 3
+    tile[(0, *sl)] = np.broadcast_to(u0.reshape(shape), tile[(0, *sl)].shape)
+    orc.grid_fill(p, tile, n, [("periodic", "periodic")] * 3)
+    nu = 0.37
+    dt = nu / (a * N)
+    rec = orc.make_dtrec(dt, ch=0.0, damp=1.0, alpha=a)
+    u1, _, _ = orc.step_tile(p, (1 / N, 1 / N, 1 / N), tile, n, rec)
+    line = np.moveaxis(u1[0], 2 - axis, 0)[:, 0, 0]
+    up, um = np.roll(u0, -1), np.roll(u0, 1)
+    dplus, dminus = up - u0, u0 - um
+    if scheme == "mmc":
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where(dplus != 0, dminus / np.where(dplus == 0, 1, dplus), 0.0)
+        f = a * u0 + 0.5 * _phi(r, "minmod") * a * (1 - nu) * dplus
+    else:
+        f = a * (u0 + 0.5 * (1 - nu) * _mm(dminus, dplus))
+    want = u0 - nu / a * (f - np.roll(f, 1))
+    np.testing.assert_allclose(line, want, rtol=0, atol=1e-13)
+    # and the tile is still uniform across the other two axes
+    assert np.all(np.moveaxis(u1[0], 2 - axis, 0) == line[:, None, None])
+
+
 def test_mmc_without_limiter_is_first_order_rusanov(orc):
     """With the flux limiter switched to zero correction (constant data on one
     side), MMC's base flux h is the Lax-Friedrichs-split upwind flux."""
