@@ -352,6 +352,16 @@ def time_regrid(sim, wl):
     return out
 
 
+def launch_label(cfg, eager):
+    """How the cycle is launched: graph or eager, batched over all blocks,
+    persistent only when the autotuner chose a persistent update grid."""
+    how = "eager" if eager else "hipGraph"
+    if cfg is None or cfg.get("mode", 0) != 0:
+        return f"{how}, one launch per block"
+    kind = "persistent" if cfg.get("grid_step", 0) > 0 else "one workgroup per work item"
+    return f"{how}, batched ({kind})"
+
+
 def time_fp64_batched(name, steps, autotune=True):
     """The LF cycle with an FP64 state on the same workload: batched
     persistent launches captured in a HIP graph, as the FP32 headline run."""
@@ -360,7 +370,7 @@ def time_fp64_batched(name, steps, autotune=True):
     wl64 = build_workload(name, "fp64")
     sim = Simulation(wl64, precision="fp64")
     sim.load_initial()
-    chosen = sim.autotune() if autotune else None
+    chosen = sim.autotune() if autotune else sim.launch_config()
     sim.graph_run(2)
     sim.sync()
     torch.cuda.synchronize()
@@ -372,8 +382,8 @@ def time_fp64_batched(name, steps, autotune=True):
     t_step = time_step_kernel(sim, 5)
     out = {"ms_per_step": el / steps * 1e3, "value": wl64.n_leaf_cells() * steps / el,
            "unit": "cell-updates/s", "steps": steps, "step_kernel_ms": t_step * 1e3,
-           "grids": chosen, "flags": [int(c) for c in cnt],
-           "note": "FP64 state and arithmetic, hipGraph, batched persistent"}
+           "launch": launch_label(chosen, False), "launch_config": chosen,
+           "flags": [int(c) for c in cnt], "note": "FP64 state and arithmetic"}
     del sim
     torch.cuda.empty_cache()
     return out
@@ -508,10 +518,10 @@ def main():
     sim = Simulation(wl, precision=args.precision)
     sim.load_initial()
     log(f"initial data on device in {time.time() - t0:.1f}s")
-    chosen = None
+    chosen = sim.launch_config()
     if not args.no_autotune:
         chosen = sim.autotune()  # trial steps write the shadow state, not U
-        log(f"autotuned grids (step, fill): {chosen}")
+        log(f"autotuned launch shapes: {chosen}")
         sim.sync()
     run = sim.advance if args.eager else sim.graph_run
     run(args.warmup)
@@ -556,8 +566,8 @@ def main():
                    "leaves": int(sim.sizes.nleaves), "leaf_cells": int(nleaf_cells),
                    "block": "16^%d + 2 ghosts" % wl.ndim, "scheme": wl.scheme,
                    "limiter": wl.limiter, "glm": wl.glm_mode, "eta": wl.eta,
-                   "state": args.precision, "launch": "eager batched" if args.eager
-                   else "hipGraph, batched persistent", "grids": chosen},
+                   "state": args.precision, "launch": launch_label(chosen, args.eager),
+                   "launch_config": chosen},
         "roofline": {"bound": "alu", "achieved": tflops, "peak": ALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": tflops / ALU_PEAK_TFLOPS, "traffic": traffic,
                      "valu_busy": valu_busy,

@@ -292,12 +292,37 @@ map_status map_graph_run(map_ctx *ctx, void *U, map_dt *dt_dev, int nsteps, void
  * workgroups of the batched step / fill launches (0 = one per work item). */
 map_status map_set_launch(map_ctx *ctx, int mode, int grid_step, int grid_fill);
 
-/* Time the batched step and fill launches over a set of grid sizes on U with
- * HIP events and keep the fastest (project autotuner); writes the chosen
- * sizes to chosen[2] if not NULL.  Synchronises `stream`.  The trial steps
- * (for WENO, first stages) write the shadow state; U's interiors are not
- * changed (ghost frames of parents that feed prolongation are rewritten
- * with the same values). */
+/* Launch shapes of the batched stages (map_set_launch sets the first three). */
+typedef struct {
+    int mode;            /* MAP_LAUNCH_BATCHED or MAP_LAUNCH_PER_BLOCK */
+    int grid_step;       /* workgroups of the update launch; 0 = one per work
+                            item, > 0 = a persistent grid striding over them */
+    int grid_fill;       /* the same for the parent-frame copies of the fill */
+    int step_shape;      /* workgroup shape of the update: 2-D LF and WENO,
+                            0 = 14 blocks in 4 waves, 1 = 7 blocks in 2 waves;
+                            3-D FP32 LF and WENO, 0 = compiled for two
+                            workgroups per CU (256 registers per lane), 1 =
+                            for one (512); 0 elsewhere */
+    int restrict_split;  /* restriction levels with fewer parents than this
+                            take one workgroup per child, the others one per
+                            parent; -1 = the number of compute units */
+    int step_blocks_per_group;  /* read only: blocks per update workgroup */
+} map_launch;
+
+map_status map_get_launch(const map_ctx *ctx, map_launch *out);
+/* Errors: MAP_EINVAL (unknown mode, negative grid, a step_shape the
+ * context's scheme and precision do not have, restrict_split < -1). */
+map_status map_set_launch_config(map_ctx *ctx, const map_launch *in);
+
+/* The launch autotuner: on U, with HIP events, times the update over its
+ * workgroup shapes and persistent grids (multiples of the CU count below the
+ * work-item count, and one workgroup per item), then the fill copies over
+ * the grids, then the restriction over the per-child split, and keeps the
+ * fastest of each (map_get_launch reports them); writes grid_step and
+ * grid_fill to chosen[2] if not NULL.  Synchronises `stream`.  The trial
+ * updates (for WENO, first stages) write the shadow state; U's interiors are
+ * not changed (the trial restrictions and copies rewrite parent interiors
+ * and parent frames with the same values). */
 map_status map_autotune(map_ctx *ctx, void *U, int *chosen, void *stream);
 
 /* ---- regrid (Sec. 4.5) ------------------------------------------------ */

@@ -151,8 +151,9 @@ map_status run_restrict(map_ctx *c, void *U, hipStream_t s, int eonly_sub = -1, 
         if (hi <= lo)
             continue;
         a.list = dptr<int32_t>(c, c->ws.restrict_list) + lo;
-        // a level with fewer parents than CUs takes one workgroup per child
-        a.per_child = hi - lo < c->ncu;
+        // a level with fewer parents than CUs (or the tuned split) takes one
+        // workgroup per child
+        a.per_child = hi - lo < (c->restrict_split >= 0 ? c->restrict_split : c->ncu);
         a.nitems = (hi - lo) * (a.per_child ? (c->nd == 3 ? 8 : 4) : 1);
         HIPCHK(launch_restrict(c->nd, fp64(c), a, s));
     }
@@ -249,6 +250,7 @@ map_status run_step_kernel(map_ctx *c, int sch, const void *Uin, void *Uout, con
     a.eglm = c->p.eglm_sources;
     a.limiter = c->p.limiter;
     a.riemann = c->p.riemann;
+    a.shape = c->step_shape;
     const bool resist = c->p.eta > 0.0;
     auto launch = [&](const StepArgs &x, int grid) -> hipError_t {
         if (c->p.scheme == MAP_MMC)
@@ -257,7 +259,7 @@ map_status run_step_kernel(map_ctx *c, int sch, const void *Uin, void *Uout, con
             return launch_step3(fp64(c), resist, sch, x, grid, s);
         return launch_step2(fp64(c), resist, sch, x, grid, s);
     };
-    const int bpw = step_blocks_per_group(c->nd, c->p.scheme);
+    const int bpw = step_blocks_per_group(c->nd, c->p.scheme, c->step_shape);
     if (c->launch_mode == MAP_LAUNCH_PER_BLOCK) {
         for (int i = 0; i < c->nleaves; i++) {
             a.leaves = dptr<int32_t>(c, c->ws.leaves) + i;
@@ -874,6 +876,43 @@ map_status map_set_launch(map_ctx *c, int mode, int grid_step, int grid_fill)
     return MAP_OK;
 }
 
+// whether the update of this context has a second workgroup shape
+static bool has_step_shapes(const map_ctx *c)
+{
+    if (c->p.scheme == MAP_MMC)
+        return false;
+    return c->nd == 2 || c->p.precision == MAP_FP32_MIXED;
+}
+
+map_status map_get_launch(const map_ctx *c, map_launch *out)
+{
+    if (!c || !out)
+        return fail(MAP_EINVAL, "null argument");
+    out->mode = c->launch_mode;
+    out->grid_step = c->grid_step;
+    out->grid_fill = c->grid_fill;
+    out->step_shape = c->step_shape;
+    out->restrict_split = c->restrict_split >= 0 ? c->restrict_split : c->ncu;
+    out->step_blocks_per_group = step_blocks_per_group(c->nd, c->p.scheme, c->step_shape);
+    return MAP_OK;
+}
+
+map_status map_set_launch_config(map_ctx *c, const map_launch *in)
+{
+    if (!c || !in)
+        return fail(MAP_EINVAL, "null argument");
+    if (in->step_shape < 0 || in->step_shape > 1 || (in->step_shape == 1 && !has_step_shapes(c)))
+        return fail(MAP_EINVAL, "step_shape 1 exists for 2-D LF/WENO and 3-D FP32 LF/WENO only");
+    if (in->restrict_split < -1)
+        return fail(MAP_EINVAL, "restrict_split below -1");
+    map_status st = map_set_launch(c, in->mode, in->grid_step, in->grid_fill);
+    if (st)
+        return st;
+    c->step_shape = in->step_shape;
+    c->restrict_split = in->restrict_split;
+    return MAP_OK;
+}
+
 map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
 {
     map_status st = need_bound(c);
@@ -884,10 +923,6 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
     hipStream_t s = S(stream);
     const int saved_mode = c->launch_mode;
     c->launch_mode = MAP_LAUNCH_BATCHED;
-    const int bpw = step_blocks_per_group(c->nd, c->p.scheme);
-    const int nstep = (c->nleaves + bpw - 1) / bpw;
-    const int fbpw = fill_blocks_per_group(c->nd);
-    const int nfill = ((int)c->frame_list.size() + fbpw - 1) / fbpw;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -908,30 +943,40 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
         }
         return best;
     };
-    // candidate persistent grids: multiples of the 256 compute units, and
-    // one workgroup per work item (0)
-    std::vector<int> cands = {0};
-    for (int m : {1, 2, 4, 8, 16})
-        if (256 * m < nstep)
-            cands.push_back(256 * m);
-    int best_step = 0;
+    // persistent grids: multiples of the compute units below the item count,
+    // and one workgroup per work item (0)
+    auto grids = [&](int nitems) {
+        std::vector<int> g = {0};
+        for (int m : {1, 2, 4, 8, 16})
+            if (c->ncu * m < nitems)
+                g.push_back(c->ncu * m);
+        return g;
+    };
+    // the update: workgroup shape x persistent grid
+    int best_shape = 0, best_step = 0;
     float best_t = 1e30f;
-    for (int g : cands) {
-        c->grid_step = g;
-        const int sch = c->p.scheme == MAP_WENO ? SCH_WENO1 : SCH_LF;
-        float t = time_it([&] { return run_step_kernel(c, sch, U, shadow(c), nullptr, dt, s); });
-        if (t < best_t) {
-            best_t = t;
-            best_step = g;
+    const int nshapes = has_step_shapes(c) ? 2 : 1;
+    for (int shape = 0; shape < nshapes; shape++) {
+        c->step_shape = shape;
+        const int bpw = step_blocks_per_group(c->nd, c->p.scheme, shape);
+        for (int g : grids((c->nleaves + bpw - 1) / bpw)) {
+            c->grid_step = g;
+            const int sch = c->p.scheme == MAP_WENO ? SCH_WENO1 : SCH_LF;
+            float t = time_it([&] { return run_step_kernel(c, sch, U, shadow(c), nullptr, dt, s); });
+            if (t < best_t) {
+                best_t = t;
+                best_shape = shape;
+                best_step = g;
+            }
         }
     }
-    std::vector<int> fc = {0};
-    for (int m : {1, 2, 4, 8, 16})
-        if (256 * m < nfill)
-            fc.push_back(256 * m);
+    c->step_shape = best_shape;
+    c->grid_step = best_step;
+    // the parent-frame copies of the cycle's fill
+    const int fbpw = fill_blocks_per_group(c->nd);
     int best_fill = 0;
     best_t = 1e30f;
-    for (int g : fc) {
+    for (int g : grids(((int)c->frame_list.size() + fbpw - 1) / fbpw)) {
         c->grid_fill = g;
         float t = time_it([&] { return run_fill(c, U, s, false); });
         if (t < best_t) {
@@ -939,12 +984,26 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
             best_fill = g;
         }
     }
+    c->grid_fill = best_fill;
+    // restriction: below how many parents a level takes one workgroup per
+    // child (it rewrites the parents' interiors with the same values)
+    int best_split = c->ncu;
+    if (c->lmax > 1) {
+        best_t = 1e30f;
+        for (int sp : {0, c->ncu / 2, c->ncu, 2 * c->ncu, 4 * c->ncu, 1 << 30}) {
+            c->restrict_split = sp;
+            float t = time_it([&] { return run_restrict(c, U, s); });
+            if (t < best_t) {
+                best_t = t;
+                best_split = sp;
+            }
+        }
+    }
+    c->restrict_split = best_split;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     drop_graph(c);
     c->launch_mode = saved_mode;
-    c->grid_step = best_step;
-    c->grid_fill = best_fill;
     if (chosen) {
         chosen[0] = best_step;
         chosen[1] = best_fill;

@@ -4,9 +4,10 @@
 // uniform resistivity (Sec. 3.5) and exact psi damping (the 3-D kernel is in
 // k_step3.hpp).
 //
-// Layout and schedule (gfx950): a workgroup of 256 threads holds 14 blocks,
-// 18 columns each (x = -1 .. 16: the interior and the cell on each side
-// whose face states feed the block's x faces).  Threads march along y, one
+// Layout and schedule (gfx950): a workgroup holds BPW blocks, 18 columns
+// each (x = -1 .. 16: the interior and the cell on each side whose face
+// states feed the block's x faces): 14 blocks in 256 threads, or 7 in 128
+// (the launch autotuner picks one).  Threads march along y, one
 // row per iteration:
 //   * y neighbours (slopes, the half-step flux, the face between rows,
 //     source and resistive differences) stay in the thread's registers;
@@ -38,16 +39,18 @@ namespace mapk {
 namespace {
 constexpr int XS2 = PD;            // row stride
 constexpr int P2 = PD * PD;        // padded tile cells
-constexpr int BPW2 = 14;           // blocks per workgroup
-constexpr int NT2 = 256;           // threads
 constexpr int NCOL2 = NB + 2;      // computing columns per block
-constexpr int NXT2 = 2 * BPW2;     // load-only cells (x = -2, x = 17) per row
+// the two workgroup shapes: blocks per workgroup and threads
+constexpr int nt_of(int bpw) { return bpw == 14 ? 256 : 128; }
 }  // namespace
 
-template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS>
-__global__ void __launch_bounds__(NT2) k_step2(StepArgs a)
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS, int BPW>
+__global__ void __launch_bounds__(nt_of(BPW)) k_step2(StepArgs a)
 {
-    constexpr int XS = XS2, BPW = BPW2, P = P2, FC = NB;
+    constexpr int XS = XS2, P = P2, FC = NB;
+    constexpr int NT2 = nt_of(BPW);
+    constexpr int NXT2 = 2 * BPW;  // load-only cells (x = -2, x = 17) per row
+    static_assert(BPW * NCOL2 <= NT2, "one thread per column");
     constexpr int SUB = BPW * NV * XS;
     __shared__ T su[2 * SUB];             // state of rows k and k-1 (by parity)
     __shared__ T srf[BPW * NV * XS];      // right face states, then fluxes
@@ -507,7 +510,12 @@ template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS>
 static hipError_t launch2(const StepArgs &a, int grid, hipStream_t s)
 {
     const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
-    hipLaunchKernelGGL((k_step2<T, MIXED, RESIST, SCH, LIM, RS>), dim3(g), dim3(NT2), 0, s, a);
+    if (a.shape == 1)
+        hipLaunchKernelGGL((k_step2<T, MIXED, RESIST, SCH, LIM, RS, 7>), dim3(g), dim3(nt_of(7)), 0,
+                           s, a);
+    else
+        hipLaunchKernelGGL((k_step2<T, MIXED, RESIST, SCH, LIM, RS, 14>), dim3(g), dim3(nt_of(14)),
+                           0, s, a);
     return hipGetLastError();
 }
 
@@ -536,11 +544,11 @@ static hipError_t launch2_rs(int sch, const StepArgs &a, int grid, hipStream_t s
     return launch2_sch<T, MIXED, RESIST, MAP_RUSANOV>(sch, a, grid, s);
 }
 
-int step_blocks_per_group(int ndim, int scheme)
+int step_blocks_per_group(int ndim, int scheme, int shape)
 {
     if (scheme == MAP_MMC || ndim == 3)
         return 1;
-    return BPW2;
+    return shape == 1 ? 7 : 14;
 }
 
 hipError_t launch_step2(bool fp64, bool resist, int sch, const StepArgs &a, int grid, hipStream_t s)

@@ -6,7 +6,8 @@
 // Schedule (gfx950): one block per workgroup of 4 waves, so that two
 // workgroups share a compute unit (the FP32 kernel keeps to 256 registers
 // and 80 KB of LDS per workgroup) and one block's waits overlap the other's
-// arithmetic.  Threads own the 16 x 16 interior columns of the block and
+// arithmetic; an FP32 instance compiled for one workgroup per CU (512
+// registers, no spills) is the launch autotuner's alternative.  Threads own the 16 x 16 interior columns of the block and
 // march along z one plane per iteration:
 //   * march-axis neighbours (slopes, the half-step flux, the face between
 //     planes, source and resistive differences) stay in the thread's
@@ -58,8 +59,8 @@ constexpr int OPW = NOUT / 4;         // outer cells per wave (20)
 static_assert(NB == 16 && NT3 == 256, "lane layout assumes 16^3 blocks");
 }  // namespace
 
-template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS>
-__global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs a)
+template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS, int OCC>
+__global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
 {
     constexpr int SY = PD;
     constexpr int SUB = NV * XS3;
@@ -664,11 +665,22 @@ __global__ void __launch_bounds__(NT3, sizeof(T) == 4 ? 2 : 1) k_step3(StepArgs 
     }
 }
 
+// FP32: compiled for two workgroups per CU (shape 0) or one (shape 1, twice
+// the registers); FP64 (148 KB of LDS) for one
 template <typename T, bool MIXED, bool RESIST, int SCH, int LIM, int RS>
 static hipError_t launch3(const StepArgs &a, int grid, hipStream_t s)
 {
     const int g = grid > 0 ? (grid < a.nitems ? grid : a.nitems) : a.nitems;
-    hipLaunchKernelGGL((k_step3<T, MIXED, RESIST, SCH, LIM, RS>), dim3(g), dim3(NT3), 0, s, a);
+    if constexpr (sizeof(T) == 4) {
+        if (a.shape == 1)
+            hipLaunchKernelGGL((k_step3<T, MIXED, RESIST, SCH, LIM, RS, 1>), dim3(g), dim3(NT3), 0,
+                               s, a);
+        else
+            hipLaunchKernelGGL((k_step3<T, MIXED, RESIST, SCH, LIM, RS, 2>), dim3(g), dim3(NT3), 0,
+                               s, a);
+    } else {
+        hipLaunchKernelGGL((k_step3<T, MIXED, RESIST, SCH, LIM, RS, 1>), dim3(g), dim3(NT3), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -29,6 +29,10 @@ struct StepArgs {
     unsigned long long *cnt;
     double gamma, eta;
     int eglm, limiter, riemann;
+    // workgroup shape of the update: 2-D LF / WENO, 0 = 14 blocks in 4 waves,
+    // 1 = 7 blocks in 2 waves; 3-D FP32 LF / WENO, 0 = compiled for two
+    // workgroups per CU (256 registers per lane), 1 = for one (512)
+    int shape;
 };
 
 // energy-only passes of a conduction sub-step (eonly = 1): only the energy
@@ -169,7 +173,8 @@ hipError_t launch_step3_ilp(int sch, const StepArgs &a, int grid, hipStream_t s)
 hipError_t launch_step_mmc(int ndim, bool fp64, const StepArgs &a, double alpha_unused, int grid,
                            hipStream_t s);
 hipError_t launch_step_mmc3(bool fp64, bool resist, const StepArgs &a, int grid, hipStream_t s);
-int step_blocks_per_group(int ndim, int scheme);
+// blocks per workgroup of the batched update for a workgroup shape (StepArgs::shape)
+int step_blocks_per_group(int ndim, int scheme, int shape);
 hipError_t launch_fill_copy(int ndim, bool fp64, const FillArgs &a, int grid, hipStream_t s);
 int fill_blocks_per_group(int ndim);
 hipError_t launch_prolong_ghosts(int ndim, bool fp64, const FillArgs &a, hipStream_t s);

@@ -50,6 +50,8 @@ struct map_ctx {
     // launch configuration
     int launch_mode = MAP_LAUNCH_BATCHED;
     int grid_step = 0, grid_fill = 0;
+    int step_shape = 0;        // workgroup shape of the update (StepArgs::shape)
+    int restrict_split = -1;   // levels with fewer parents take one workgroup per child (-1: ncu)
     int ncu = 256;  // compute units of the bound device
 
     // map_remap: by slot, the source slot in the previous tree (-1: new

@@ -35,7 +35,8 @@ EXPORTS = ["map_init_blocks", "map_query", "map_neighbors", "map_fill_selection"
            "map_prim_to_cons", "map_fill_ghosts", "map_restrict", "map_prolong", "map_cfl_dt",
            "map_step", "map_reflux", "map_conduct", "map_totals", "map_totals_static",
            "map_status_flags", "map_advance",
-           "map_graph_run", "map_set_launch", "map_autotune", "map_estimate", "map_regrid",
+           "map_graph_run", "map_set_launch", "map_get_launch", "map_set_launch_config",
+           "map_autotune", "map_estimate", "map_regrid",
            "map_remap", "map_last_error", "map_destroy"]
 
 
@@ -79,6 +80,15 @@ class map_sizes(C.Structure):
                 ("max_level", C.c_int), ("tile_cells", C.c_int), ("nvar", C.c_int),
                 ("n_prolong_items", C.c_int), ("n_reflux_blocks", C.c_int),
                 ("n_face_buffers", C.c_int)]
+
+
+class map_launch(C.Structure):
+    _fields_ = [("mode", C.c_int), ("grid_step", C.c_int), ("grid_fill", C.c_int),
+                ("step_shape", C.c_int), ("restrict_split", C.c_int),
+                ("step_blocks_per_group", C.c_int)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
 
 
 class map_estimator(C.Structure):
@@ -125,6 +135,8 @@ def lib():
         L.map_graph_run.argtypes = [vp, vp, vp, C.c_int, vp]
         L.map_set_launch.argtypes = [vp, C.c_int, C.c_int, C.c_int]
         L.map_autotune.argtypes = [vp, vp, C.POINTER(C.c_int), vp]
+        L.map_get_launch.argtypes = [vp, C.POINTER(map_launch)]
+        L.map_set_launch_config.argtypes = [vp, C.POINTER(map_launch)]
         L.map_estimate.argtypes = [vp, vp, C.POINTER(map_estimator), vp, vp]
         L.map_regrid.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(map_regrid_params),
                                  C.POINTER(map_block_key), C.c_int, C.POINTER(C.c_int)]
@@ -301,6 +313,21 @@ def map_autotune(ctx, U, stream):
     arr = (C.c_int * 2)()
     check(lib().map_autotune(ctx, _p(U), arr, _p(stream)))
     return int(arr[0]), int(arr[1])
+
+
+def map_get_launch(ctx) -> dict:
+    out = map_launch()
+    check(lib().map_get_launch(ctx, C.byref(out)))
+    return out.as_dict()
+
+
+def map_set_launch_config(ctx, cfg: dict):
+    x = map_launch()
+    cur = map_get_launch(ctx)
+    cur.update(cfg)
+    for k, _ in map_launch._fields_:
+        setattr(x, k, int(cur[k]))
+    check(lib().map_set_launch_config(ctx, C.byref(x)))
 
 
 def make_estimator(criteria, filt=0.05, bias=0.6, ratio=2.0, xi=0.0):

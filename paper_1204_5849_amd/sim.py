@@ -144,7 +144,15 @@ class Simulation:
         N.map_set_launch(self.ctx, mode, grid_step, grid_fill)
 
     def autotune(self):
-        return N.map_autotune(self.ctx, self.U, self.sp)
+        """Pick the launch shapes (map_autotune) and return them (map_get_launch)."""
+        N.map_autotune(self.ctx, self.U, self.sp)
+        return N.map_get_launch(self.ctx)
+
+    def launch_config(self) -> dict:
+        return N.map_get_launch(self.ctx)
+
+    def set_launch_config(self, **cfg):
+        N.map_set_launch_config(self.ctx, cfg)
 
     # ---------------------------------------------------------------- regrid
     def estimate(self, criteria, filt=0.05, bias=0.6, ratio=2.0, xi=0.0):

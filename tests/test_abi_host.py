@@ -245,7 +245,7 @@ def test_each_step_instance_is_compiled_once():
     """The 3-D step kernel template is instantiated from two translation units
     compiled with different instruction schedulers; an instance defined in
     both would leave the linker to pick one of the two copies, so the sets of
-    instances must be disjoint (and together hold all 40)."""
+    instances must be disjoint (and together hold all 60)."""
     import shutil
     import subprocess
     from paper_1204_5849_amd import build as B
@@ -257,8 +257,9 @@ def test_each_step_instance_is_compiled_once():
         out = subprocess.run(["nm", "-C", o], capture_output=True, text=True, check=True).stdout
         sets.append(set(re.findall(r"k_step3<([^>]*)>", out)))
     assert not (sets[0] & sets[1]), sorted(sets[0] & sets[1])
-    # 2 precisions x 2 (resistivity) x (3 LF limiters + 2 WENO stages) x 2 fluxes
-    assert len(sets[0] | sets[1]) == 40
+    # 2 precisions x 2 (resistivity) x (3 LF limiters + 2 WENO stages) x 2 fluxes,
+    # the FP32 ones for two workgroups per CU and for one
+    assert len(sets[0] | sets[1]) == 60
 
 
 def test_totals_static_rejects_too_many_leaves():
@@ -274,5 +275,39 @@ def test_totals_static_rejects_too_many_leaves():
         assert st == N.MAP_EINVAL
         msg = N.lib().map_last_error().decode()
         assert "static scratch" in msg and "58254" in msg, msg
+    finally:
+        N.map_destroy(ctx)
+
+
+def test_launch_config_checks():
+    """map_get_launch / map_set_launch_config on the host: defaults, and the
+    workgroup shapes a scheme and precision do not have are rejected."""
+    from paper_1204_5849_amd import native as N
+    from paper_1204_5849_amd import workloads as W
+    w2 = W.orszag_tang(2)
+    w3 = W.harris3d(nbase=2, levels=1)
+    cases = [(N.make_params(2), w2, True), (N.make_params(2, scheme="mmc"), w2, False),
+             (N.make_params(3, precision="fp32"), w3, True), (N.make_params(3), w3, False),
+             (N.make_params(3, precision="fp32", scheme="mmc"), w3, False)]
+    for p, w, shape1 in cases:
+        ctx = N.map_init_blocks(p, w.sims, w.keys)
+        try:
+            cfg = N.map_get_launch(ctx)
+            assert cfg["mode"] == N.MAP_LAUNCH_BATCHED and cfg["grid_step"] == 0
+            assert cfg["step_shape"] == 0
+            if shape1:
+                N.map_set_launch_config(ctx, {"step_shape": 1})
+                assert N.map_get_launch(ctx)["step_shape"] == 1
+            else:
+                with pytest.raises(N.MapError):
+                    N.map_set_launch_config(ctx, {"step_shape": 1})
+            with pytest.raises(N.MapError):
+                N.map_set_launch_config(ctx, {"restrict_split": -2})
+        finally:
+            N.map_destroy(ctx)
+    ctx = N.map_init_blocks(N.make_params(2), w2.sims, w2.keys)
+    try:
+        N.map_set_launch_config(ctx, {"step_shape": 1})
+        assert N.map_get_launch(ctx)["step_blocks_per_group"] == 7
     finally:
         N.map_destroy(ctx)

@@ -1,0 +1,65 @@
+"""Launch shapes (the autotuner's search space) change nothing in the
+results: every workgroup shape, persistent grid and restriction split gives
+the state of the default launch bit for bit."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_1204_5849_amd import native as N  # noqa: E402
+from paper_1204_5849_amd import workloads as W  # noqa: E402
+from tests.test_gpu_parity import _sim, _tree, _tree_ic  # noqa: E402
+
+
+def _say(msg):
+    print(f"[gpu-launch] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    N.lib()
+    return "cuda:0"
+
+
+CONFIGS = [dict(step_shape=1), dict(grid_step=256, grid_fill=256), dict(restrict_split=0),
+           dict(restrict_split=1 << 30), dict(step_shape=1, grid_step=512, restrict_split=64)]
+
+
+@pytest.mark.parametrize("ndim,scheme,precision", [(2, "lf", "fp64"), (2, "weno", "fp32"),
+                                                   (3, "lf", "fp32"), (3, "weno", "fp32")])
+def test_launch_shapes_give_the_same_state(dev, ndim, scheme, precision):
+    sims, keys = _tree(ndim, 61 + ndim, "mixed")
+    w = W.Workload(name="tree", ndim=ndim, sims=sims, keys=keys, ic=_tree_ic, scheme=scheme,
+                   precision=precision, eta=1e-3 if ndim == 3 else 0.0)
+    ref = _sim(w)
+    ref.graph_run(3)
+    ref.fill()
+    want = ref.state_by_key()
+    for cfg in CONFIGS:
+        s = _sim(w)
+        s.set_launch_config(**cfg)
+        got_cfg = s.launch_config()
+        s.graph_run(3)
+        s.fill()
+        _say(f"ndim={ndim} {scheme} {precision} {got_cfg}")
+        assert np.array_equal(s.state_by_key(), want), cfg
+
+
+def test_autotune_picks_from_its_search_space(dev):
+    w = dataclasses.replace(W.harris3d(nbase=4, levels=3, precision="fp32"))
+    s = _sim(w)
+    u0 = s.state_by_key()
+    cfg = s.autotune()
+    _say(f"harris 64^3 L3 fp32 autotuned: {cfg}")
+    assert cfg["step_shape"] in (0, 1) and cfg["grid_step"] % 256 == 0
+    assert cfg["restrict_split"] >= 0
+    # the trials leave U's interiors and parent frames as they were
+    leaves = w.leaf_mask()
+    got = s.state_by_key()
+    assert np.array_equal(got[leaves][:, :, 2:-2, 2:-2, 2:-2], u0[leaves][:, :, 2:-2, 2:-2, 2:-2])
