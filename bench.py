@@ -280,6 +280,109 @@ def cpu_baseline_and_l1(cycles=10, one_core_cycles=3):
     return base, l1_out
 
 
+def leaf_rel_l1(w, sim, A):
+    """Volume-weighted relative L1 of the GPU state (sim) against the oracle's
+    (A) over leaf interiors, per variable and for |B|."""
+    leaves = np.nonzero(w.leaf_mask())[0]
+    num, den = np.zeros(10), np.zeros(10)
+    ng = 2
+    for s0 in range(0, len(leaves), 2048):
+        idx = leaves[s0:s0 + 2048]
+        g, o = sim.state_by_key(idx), A.state[idx]
+        if w.ndim == 3:
+            g, o = g[:, :, ng:-ng, ng:-ng, ng:-ng], o[:, :, ng:-ng, ng:-ng, ng:-ng]
+        else:
+            g, o = g[:, :, :, ng:-ng, ng:-ng], o[:, :, :, ng:-ng, ng:-ng]
+        vol = np.array([np.prod(w.dx(int(k[0]), int(k[1]))[:w.ndim]) for k in w.keys[idx]])
+        vol = vol[:, None, None, None]
+        for k in range(9):
+            num[k] += float((np.abs(g[:, k] - o[:, k]) * vol).sum())
+            den[k] += float((np.abs(o[:, k]) * vol).sum())
+        bg, bo = np.sqrt((g[:, 4:7] ** 2).sum(axis=1)), np.sqrt((o[:, 4:7] ** 2).sum(axis=1))
+        num[9] += float((np.abs(bg - bo) * vol).sum())
+        den[9] += float((np.abs(bo) * vol).sum())
+    names = ["rho", "mx", "my", "mz", "Bx", "By", "Bz", "e", "psi", "absB"]
+    return {n: num[i] / max(den[i], 1e-300) for i, n in enumerate(names)}
+
+
+def time_cycles(sim, steps, graph=True):
+    """Wall time per cycle of `steps` cycles (after two warm-up cycles)."""
+    import torch
+    run = sim.graph_run if graph else sim.advance
+    run(2)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run(steps)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def measure_config(key, precision_b, precision_p, steps_b, steps_p, l1_cycles=0,
+                   plain_graph=False, batched_only=False):
+    """One configuration besides the headline: its batched path (autotuned,
+    graph-captured) in precision_b, its per-block ("plain") path in
+    precision_p (one launch per block and stage), and, if l1_cycles, the
+    batched path's relative L1 against the FP64 oracle after that many whole
+    cycles from the same initial data."""
+    import torch
+    import oracle as orc
+    from paper_1204_5849_amd.sim import Simulation
+    wb = build_workload(key, precision_b)
+    cells = wb.n_leaf_cells()
+    out = {"workload": wb.name, "blocks": int(len(wb.keys)), "leaves": int(wb.leaf_mask().sum()),
+           "leaf_cells": int(cells), "simulations": len(wb.sims), "scheme": wb.scheme,
+           "limiter": wb.limiter}
+    sim = Simulation(wb, precision=precision_b)
+    sim.load_initial()
+    cfg = sim.autotune()
+    tb = time_cycles(sim, steps_b)
+    st, cnt = sim.flags()
+    out["batched"] = {"precision": precision_b, "value": cells / tb, "ms_per_step": tb * 1e3,
+                      "steps": steps_b, "launch": launch_label(cfg, False),
+                      "launch_config": cfg, "flags": [int(c) for c in cnt]}
+    del sim
+    torch.cuda.empty_cache()
+    if batched_only:
+        return out
+    wp = build_workload(key, precision_p)
+    p = Simulation(wp, precision=precision_p, launch="per_block")
+    p.load_initial()
+    tp = time_cycles(p, steps_p, graph=plain_graph)
+    out["plain"] = {"precision": precision_p, "value": cells / tp, "ms_per_step": tp * 1e3,
+                    "steps": steps_p, "launch": "one launch per block and stage"}
+    out["speedup_batched_vs_plain"] = tp / tb
+    del p
+    torch.cuda.empty_cache()
+    if l1_cycles:
+        w64 = build_workload(key, "fp64")
+        orc.build(force=False)
+        orc.set_threads(host_threads())
+        A = orc.load_workload(w64)
+        A.run(l1_cycles)
+        orc.set_threads(1)
+        q = Simulation(wb, precision=precision_b)
+        q.load_initial()
+        q.set_launch_config(**{k: v for k, v in cfg.items() if k != "step_blocks_per_group"})
+        q.graph_run(l1_cycles)
+        q.sync()
+        out["rel_l1_vs_oracle"] = {"cycles": l1_cycles, "precision": precision_b,
+                                   **leaf_rel_l1(w64, q, A)}
+        del q, A
+        torch.cuda.empty_cache()
+    return out
+
+
+# the configurations measured besides the headline: key -> (batched precision,
+# plain precision, batched cycles, plain cycles, oracle L1 cycles)
+CONFIGS = {
+    "orszag_tang": ("fp64", "fp64", 100, 20, 100),
+    "ot_amr": ("fp64", "fp64", 100, 5, 20),
+    "blast3d": ("fp32", "fp64", 20, 2, 10),
+    "kh_ensemble": ("fp32", "fp32", 50, 3, 10),
+}
+
+
 def cycle_bytes_per_cell(wl, word):
     """Algorithmic bytes of one whole cycle per leaf cell, counted for a
     padded-ghost per-block method (the fill reads and writes the ghost frame,
@@ -489,6 +592,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true", help="eager launches instead of the graph")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations")
+    ap.add_argument("--configs-only", default=None, metavar="KEYS",
+                    help="only measure these configurations (comma-separated keys of CONFIGS)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="with --configs-only: time the batched path alone (for kernel traces)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (counter calibration)")
     args = ap.parse_args()
@@ -509,6 +618,15 @@ def main():
 
     import torch
     from paper_1204_5849_amd.sim import Simulation
+
+    if args.configs_only:
+        res = {}
+        for key in args.configs_only.split(","):
+            log(f"configuration {key}")
+            r = measure_config(key, *CONFIGS[key], batched_only=args.batched_only)
+            res[r["workload"]] = r
+        print(json.dumps({"configs": res}), flush=True)
+        return
 
     wl = build_workload(args.workload, args.precision)
     nleaf_cells = wl.n_leaf_cells()
@@ -642,6 +760,17 @@ def main():
                                 "steps": args.plain_steps, "launch": "one launch per block",
                                 "speedup_of_value": value / plain_rate}
         log(f"fp64 plain {plain_rate / 1e9:.3f} G cell-updates/s")
+
+    if not args.no_configs:
+        result["configs"] = {}
+        for key, spec in CONFIGS.items():
+            log(f"configuration {key}: batched {spec[0]} vs plain {spec[1]}")
+            r = measure_config(key, *spec)
+            result["configs"][r["workload"]] = r
+            l1 = r.get("rel_l1_vs_oracle", {})
+            log(f"  {r['batched']['value'] / 1e9:.3f} G vs {r['plain']['value'] / 1e9:.4f} G "
+                f"cell-updates/s (x{r['speedup_batched_vs_plain']:.0f}); L1 rho "
+                f"{l1.get('rho', float('nan')):.2e}")
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) and the FP32 path's L1 against it")
