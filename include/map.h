@@ -371,6 +371,17 @@ typedef struct {
 map_status map_regrid(const map_ctx *ctx, const double *err_host, const map_regrid_params *rp,
                       map_block_key *keys_out, int capacity, int *nout);
 
+/* When to regrid next (Sec. 4.5): per simulation, the simulated time the
+ * fastest wave needs to cross the 2 n_g buffer cells the estimate covers,
+ * dtr = c_r 2 n_g dx_min / alpha_g (dx_min the finest leaf cell width,
+ * alpha_g from the record; equal to c_r 2 n_g n_dim dt / c_cfl when dt is
+ * the CFL step), written to dtr_host[nsims], and the number of whole steps
+ * of the record's dt in it, at least 1, to steps_host[nsims].  dt_host:
+ * host copies of the last step's records.  Host only.  Errors: MAP_EINVAL
+ * (null argument, c_r <= 0, a record without a positive dt). */
+map_status map_regrid_interval(const map_ctx *ctx, const map_dt *dt_host, double c_r,
+                               double *dtr_host, int *steps_host);
+
 /* Moves a state onto a new tree of the same simulations and parameters
  * (Sec. 4.5 with the boundary procedure of Sec. 4.3): blocks present in
  * both trees are copied; blocks new in dst (children of src leaves) are

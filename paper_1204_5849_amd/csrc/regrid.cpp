@@ -2,6 +2,7 @@
 // flagged leaves, destroy the children of smooth blocks, close the result
 // under 2:1 balance.  Host only; the estimates come from map_estimate.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <unordered_map>
@@ -186,5 +187,27 @@ extern "C" map_status map_regrid(const map_ctx *c, const double *err, const map_
         return regrid_fail(MAP_ENOMEM, "keys_out holds " + std::to_string(capacity) + " keys, need " +
                                            std::to_string(out.size()));
     std::memcpy(keys_out, out.data(), out.size() * sizeof(map_block_key));
+    return MAP_OK;
+}
+
+// The interval to the next regrid (Sec. 4.5): the time the fastest wave
+// needs to cross the 2 n_g cells of the buffer zone that the estimate
+// covers, at the simulation's finest leaf cell width.
+extern "C" map_status map_regrid_interval(const map_ctx *c, const map_dt *dt_host, double c_r,
+                                          double *dtr_host, int *steps_host)
+{
+    if (!c || !dt_host || !dtr_host || !steps_host)
+        return regrid_fail(MAP_EINVAL, "null argument");
+    if (!(c_r > 0.0))
+        return regrid_fail(MAP_EINVAL, "c_r must be positive");
+    for (size_t s = 0; s < c->simrec.size(); s++) {
+        const double dt = dt_host[s].dt, alpha = dt_host[s].alpha;
+        if (!(dt > 0.0) || !(alpha >= 0.0))
+            return regrid_fail(MAP_EINVAL, "dt record " + std::to_string(s) + " has no positive dt");
+        const double dtr = alpha > 0.0 ? c_r * 2.0 * NG * c->simrec[s].dxmin / alpha : HUGE_VAL;
+        dtr_host[s] = dtr;
+        const double n = std::floor(dtr / dt);
+        steps_host[s] = n < 1.0 ? 1 : (n > 1e9 ? 1000000000 : (int)n);
+    }
     return MAP_OK;
 }

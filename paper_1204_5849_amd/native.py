@@ -36,7 +36,7 @@ EXPORTS = ["map_init_blocks", "map_query", "map_neighbors", "map_fill_selection"
            "map_step", "map_reflux", "map_conduct", "map_totals", "map_totals_static",
            "map_status_flags", "map_advance",
            "map_graph_run", "map_set_launch", "map_get_launch", "map_set_launch_config",
-           "map_autotune", "map_estimate", "map_regrid",
+           "map_autotune", "map_estimate", "map_regrid", "map_regrid_interval",
            "map_remap", "map_last_error", "map_destroy"]
 
 
@@ -141,6 +141,8 @@ def lib():
         L.map_regrid.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(map_regrid_params),
                                  C.POINTER(map_block_key), C.c_int, C.POINTER(C.c_int)]
         L.map_remap.argtypes = [vp, vp, vp, vp, vp]
+        L.map_regrid_interval.argtypes = [vp, C.POINTER(map_dt), C.c_double,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_int)]
         L.map_last_error.restype = C.c_char_p
         L.map_last_error.argtypes = []
         L.map_destroy.argtypes = [vp]
@@ -345,6 +347,20 @@ def make_estimator(criteria, filt=0.05, bias=0.6, ratio=2.0, xi=0.0):
 
 def map_estimate(ctx, U, est, err_dev, stream):
     check(lib().map_estimate(ctx, _p(U), C.byref(est), _p(err_dev), _p(stream)))
+
+
+def map_regrid_interval(ctx, dt_host, c_r):
+    """(dtr per simulation, steps per simulation) from host dt records
+    (float64 numpy [nsims, DT_WORDS])."""
+    import numpy as np
+    rec = np.ascontiguousarray(np.asarray(dt_host, dtype=np.float64))
+    ns = rec.shape[0]
+    dtr = np.zeros(ns)
+    steps = np.zeros(ns, dtype=np.int32)
+    check(lib().map_regrid_interval(ctx, rec.ctypes.data_as(C.POINTER(map_dt)), float(c_r),
+                                    dtr.ctypes.data_as(C.POINTER(C.c_double)),
+                                    steps.ctypes.data_as(C.POINTER(C.c_int))))
+    return dtr, steps
 
 
 def map_regrid(ctx, err_host, tau_refine, tau_coarsen, max_level):

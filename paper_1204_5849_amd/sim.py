@@ -32,24 +32,39 @@ class Simulation:
                                     kappa_exp=wl.kappa_exp,
                                     eglm_sources=wl.eglm_sources, gamma=wl.gamma, cfl=wl.cfl,
                                     cd=wl.cd, cr=wl.cr, eta=wl.eta)
+        self.stream = stream or torch.cuda.Stream(device=self.device)
+        with torch.cuda.device(self.device):
+            self.dt = torch.zeros((len(wl.sims), N.DT_WORDS), dtype=torch.float64, device=self.device)
+        self._spare = None  # the second pair of buffers of in-place regrids
         self.ctx = N.map_init_blocks(self.params, wl.sims, wl.keys)
+        self._plan(wl)
+        self._ubuf = torch.zeros(self._u_elems(), dtype=self.dtype, device=self.device)
+        self._wsbuf = torch.zeros(self.sizes.workspace_bytes + 256, dtype=torch.uint8,
+                                  device=self.device)
+        self._bind()
+        if launch == "per_block":
+            N.map_set_launch(self.ctx, N.MAP_LAUNCH_PER_BLOCK)
+
+    def _plan(self, wl):
+        """Sizes and slots of the context's tree."""
+        self.wl = wl
         self.sizes, self.slot_of_key = N.map_query(self.ctx)
         self.nslots = self.sizes.nblocks
         self.tile = self.sizes.tile_cells
-        self.stream = stream or torch.cuda.Stream(device=self.device)
         pz = PD if wl.ndim == 3 else 1
         self.shape = (self.nslots, NV, pz, PD, PD)
-        with torch.cuda.device(self.device):
-            self.U = torch.zeros(self.shape, dtype=self.dtype, device=self.device)
-            self.ws = torch.zeros(self.sizes.workspace_bytes + 256, dtype=torch.uint8,
-                                  device=self.device)
-            self.dt = torch.zeros((len(wl.sims), N.DT_WORDS), dtype=torch.float64, device=self.device)
+
+    def _u_elems(self):
+        return self.nslots * NV * self.tile
+
+    def _bind(self):
+        """State view and workspace of the current context on the current
+        buffers (which may be larger than the tree needs)."""
+        self.U = self._ubuf[:self._u_elems()].view(self.shape)
+        self.ws = self._wsbuf
         torch.cuda.synchronize(self.device)
-        base = self.ws.data_ptr()
-        self._ws_ptr = (base + 255) & ~255
+        self._ws_ptr = (self._wsbuf.data_ptr() + 255) & ~255
         N.map_bind_workspace(self.ctx, self._ws_ptr, self.sizes.workspace_bytes, self.sp)
-        if launch == "per_block":
-            N.map_set_launch(self.ctx, N.MAP_LAUNCH_PER_BLOCK)
 
     @property
     def sp(self):
@@ -166,10 +181,73 @@ class Simulation:
         return err.cpu().numpy()[self.slot_of_key]
 
     def regrid_interval(self, c_r=1.0):
-        """Steps between regrids, Sec. 4.5: dt_r = c_r 2 n_g n_dim dt / c_cfl
-        (a wave cannot cross the 2 n_g buffer cells of a refined region in
-        that time)."""
-        return max(1, int(c_r * 2 * NG * self.wl.ndim / self.wl.cfl))
+        """(simulated time, whole steps) until the next regrid per simulation,
+        from the last dt records (map_regrid_interval, Sec. 4.5)."""
+        self.stream.synchronize()
+        return N.map_regrid_interval(self.ctx, self.dt.cpu().numpy(), c_r)
+
+    def regrid_in_place(self, criteria, tau_refine, tau_coarsen, max_level, **est_kw):
+        """One regrid that re-plans this simulation in place: estimate on
+        device, tree edit on the host, a new context bound to the second pair
+        of state and workspace buffers, the state moved onto it, and the two
+        pairs swapped.  A pair that is too small for the new tree is replaced
+        by one of twice the tree's size, so once the tree sizes settle the
+        regrids allocate nothing.  The launch shapes carry over."""
+        import dataclasses
+        est = N.make_estimator(criteria, **est_kw)
+        err = torch.zeros(self.nslots, dtype=torch.float64, device=self.device)
+        torch.cuda.synchronize(self.device)
+        N.map_estimate(self.ctx, self.U, est, err, self.sp)
+        self.stream.synchronize()
+        keys = N.map_regrid(self.ctx, err.cpu().numpy(), tau_refine, tau_coarsen, max_level)
+        cfg = N.map_get_launch(self.ctx)
+        new_ctx = N.map_init_blocks(self.params, self.wl.sims, keys)
+        sizes, _ = N.map_query(new_ctx)
+        u_need = sizes.nblocks * NV * sizes.tile_cells
+        ws_need = sizes.workspace_bytes + 256
+        if self._spare is None:
+            self._spare = (torch.zeros(2 * u_need, dtype=self.dtype, device=self.device),
+                           torch.zeros(2 * ws_need, dtype=torch.uint8, device=self.device))
+        ubuf, wsbuf = self._spare
+        if ubuf.numel() < u_need:  # a tree larger than this pair has held
+            ubuf = torch.zeros(2 * u_need, dtype=self.dtype, device=self.device)
+        if wsbuf.numel() < ws_need:
+            wsbuf = torch.zeros(2 * ws_need, dtype=torch.uint8, device=self.device)
+        old_ctx, old_U = self.ctx, self.U
+        old_bufs = (self._ubuf, self._wsbuf)
+        self.ctx = new_ctx
+        self._plan(dataclasses.replace(self.wl, keys=keys))
+        self._ubuf, self._wsbuf = ubuf, wsbuf
+        self._bind()
+        N.map_set_launch_config(self.ctx, {k: v for k, v in cfg.items()
+                                           if k != "step_blocks_per_group"})
+        N.map_remap(self.ctx, self.U, old_ctx, old_U, self.sp)  # synchronises the stream
+        N.map_destroy(old_ctx)
+        self._spare = old_bufs
+        return keys
+
+    def run_adaptive(self, nsteps, criteria, tau_refine, tau_coarsen, max_level, c_r=1.0,
+                     graph=True, **est_kw):
+        """nsteps cycles with the regrids of Sec. 4.5 inside the run: after
+        every regrid (and at the start) the interval to the next one comes
+        from the last dt records (map_regrid_interval; the whole steps of dt
+        in c_r 2 n_g dx_min / alpha_g, the smallest over the simulations);
+        the simulation is re-planned in place.  Returns [(cycle, nblocks)]
+        of the regrids done."""
+        run = self.graph_run if graph else self.advance
+        done, log = 0, []
+        self.stream.synchronize()
+        if not bool(self.dt[:, 0].gt(0).all()):
+            self.cfl()
+        while done < nsteps:
+            _, steps = self.regrid_interval(c_r)
+            n = min(int(steps.min()), nsteps - done)
+            run(n)
+            done += n
+            if done < nsteps:
+                self.regrid_in_place(criteria, tau_refine, tau_coarsen, max_level, **est_kw)
+                log.append((done, self.nslots))
+        return log
 
     def regrid(self, criteria, tau_refine, tau_coarsen, max_level, **est_kw):
         """One regrid: estimate on device, the tree edit on the host, and the

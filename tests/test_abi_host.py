@@ -311,3 +311,30 @@ def test_launch_config_checks():
         assert N.map_get_launch(ctx)["step_blocks_per_group"] == 7
     finally:
         N.map_destroy(ctx)
+
+
+def test_regrid_interval_formula():
+    """map_regrid_interval (Sec. 4.5): dtr = c_r 2 n_g dx_min / alpha_g per
+    simulation and the whole steps of dt in it; with the CFL dt this is
+    c_r 2 n_g n_dim dt / c_cfl."""
+    from paper_1204_5849_amd import native as N
+    from paper_1204_5849_amd import workloads as W
+    w = W.orszag_tang(2)  # 32 x 32 cells on the unit square: dx_min = 1/32
+    ctx = N.map_init_blocks(N.make_params(2), w.sims, w.keys)
+    try:
+        rec = np.zeros((1, N.DT_WORDS))
+        rec[0, 0], rec[0, 3] = 1e-3, 2.0
+        dtr, steps = N.map_regrid_interval(ctx, rec, 1.0)
+        assert dtr[0] == pytest.approx(2 * 2 * (1 / 32) / 2.0, rel=1e-15)
+        assert steps[0] == 62
+        cfl, alpha, dx = 0.4, 1.7, 1 / 32
+        rec[0, 0], rec[0, 3] = cfl * dx / (2 * alpha), alpha
+        dtr, steps = N.map_regrid_interval(ctx, rec, 0.5)
+        assert dtr[0] == pytest.approx(0.5 * 2 * 2 * 2 * rec[0, 0] / cfl, rel=1e-14)
+        assert steps[0] in (9, 10)  # 0.5 * 2 n_g n_dim / c_cfl = 10, up to rounding
+        for bad_cr, bad_dt in ((0.0, 1e-3), (1.0, 0.0)):
+            rec[0, 0] = bad_dt
+            with pytest.raises(N.MapError):
+                N.map_regrid_interval(ctx, rec, bad_cr)
+    finally:
+        N.map_destroy(ctx)

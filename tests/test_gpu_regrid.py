@@ -223,3 +223,36 @@ def test_regrid_then_cycles_match_oracle(dev, orc, name):
          f"rel Linf per var {np.array2string(err8, precision=2)}")
     assert created > 0
     assert np.all(err8[:8] <= 1e-11)
+
+
+def test_run_adaptive_equals_manual_regrids(dev):
+    """Regrids inside the run at the Sec. 4.5 interval, re-planned in place:
+    the same cycles and regrids done by hand with new contexts give the same
+    trees and, bit for bit, the same state; once both buffer pairs have held
+    a tree, the regrids reuse them."""
+    w = _tree2d("fp64")
+    a = _sim(w)
+    err0 = a.estimate(CRIT)
+    tr, tc = _thresholds(w, err0)
+    log = a.run_adaptive(9, CRIT, tr, tc, 3, c_r=0.1)
+    _say(f"adaptive run: regrids at {log}")
+    assert len(log) >= 3
+    ptrs = []
+    b = _sim(w)
+    done = 0
+    for cyc, nb in log:
+        b.graph_run(cyc - done)
+        done = cyc
+        b = b.regrid(CRIT, tr, tc, 3)
+        assert len(b.wl.keys) == nb
+    b.graph_run(9 - done)
+    assert np.array_equal(a.wl.keys, b.wl.keys)
+    a.fill()
+    b.fill()
+    assert np.array_equal(a.state_by_key(), b.state_by_key())
+    # two more regrids in place: the state buffers alternate between two pairs
+    for _ in range(2):
+        a.regrid_in_place(CRIT, tr, tc, 3)
+        ptrs.append(a._ubuf.data_ptr())
+    a.regrid_in_place(CRIT, tr, tc, 3)
+    assert a._ubuf.data_ptr() == ptrs[0]
