@@ -412,15 +412,28 @@ def test_determinism_3d(dev):
     assert np.array_equal(a.state_by_key(), b.state_by_key())
 
 
-@pytest.mark.parametrize("name", ["ot", "blast"])
+@pytest.mark.parametrize("name", ["ot", "blast", "ot_amr", "tree2d"])
 def test_fp32_mixed_l1_vs_fp64_oracle(dev, name):
     """FP32 state with FP64 pressure recovery and CFL against the FP64 oracle:
-    relative L1 of rho, e and |B| <= 1e-4 (OT 100 steps, blast 10 steps)."""
+    relative L1 of rho, e and |B| <= 1e-4 (OT 100 steps, blast 10 steps, the
+    3840-block OT AMR grid with MMC + van Leer 20 steps, a random 2-D 2:1 tree
+    with outflow sides 20 steps; the last three cross coarse-fine faces, so
+    reflux, restriction and ghost prolongation enter the error)."""
+    import os
     import oracle as orc
     if name == "ot":
         w, n = W.orszag_tang(8, precision="fp32"), 100
-    else:
+    elif name == "blast":
         w, n = W.blast3d(nbase=2, levels=2, precision="fp32"), 10
+    elif name == "ot_amr":
+        path = os.path.join(os.path.dirname(__file__), "golden", "ot_amr_grid.txt")
+        w, n = W.ot_amr(np.loadtxt(path, dtype=np.int32, comments="#"), precision="fp32"), 20
+    else:
+        sims, keys = _tree(2, 23, "outflow")
+        w = W.Workload(name="tree", ndim=2, sims=sims, keys=keys, ic=_tree_ic, precision="fp32")
+        n = 20
+    if name != "ot":
+        assert not w.leaf_mask().all()  # the tree has parents: coarse-fine faces
     _say(f"fp32 vs fp64 oracle {name} {n} steps")
     s = _sim(w)
     A = orc.load_workload(w)
