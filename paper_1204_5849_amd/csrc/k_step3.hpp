@@ -15,10 +15,12 @@
 //     a time (state, right face states, face fluxes, eta J);
 //   * the ring of cells just outside the interior (minus its corners) feeds
 //     the block's boundary faces: lanes 0-15 of wave w own the ring side w
-//     (x = -1, x = 16, y = -1, y = 16), load its cells two planes ahead
-//     through a small LDS buffer, and run a reduced pass over them -- for LF
-//     the predictor, then the one face state the interior reads, and, on the
-//     -1 sides, the flux of that face;
+//     (x = -1, x = 16, y = -1, y = 16) and load its cells two planes ahead
+//     through a small LDS buffer; the reduced pass over a plane's 64 ring
+//     cells (for LF the predictor, then the one face state the interior
+//     reads) runs on one wave, one lane per cell, the wave taking turns
+//     with the plane index, so that the other three waves issue nothing for
+//     it; lanes 0-15 of the waves of the -1 sides form the flux of that face;
 //   * lanes 16-35 of each wave load the remaining cells of the padded plane
 //     (outer ring and ring corners), one plane ahead;
 //   * interior columns read their planes from the block itself or, for the
@@ -112,6 +114,15 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
     // the ring cell is the left state of the face -1/2 (x or y = -1)
     const int rdim = wv >> 1;
     const bool rlo = (wv & 1) == 0;
+    // ring-pass role (every lane of the wave that runs the ring pass of a
+    // plane): ring cell ln, on side ln / 16
+    const int rsd = ln >> 4, rix = ln & 15;
+    const int rex = rsd == 0 ? -1 : (rsd == 1 ? NB : rix);
+    const int rey = rsd == 2 ? -1 : (rsd == 3 ? NB : rix);
+    const int xqr = (rey + NG) * PD + rex + NG;
+    const int rir = ln;
+    const int rdr = rsd >> 1;
+    const bool rlr = (rsd & 1) == 0;
 
     Phys<T, MIXED> ph;
     ph.gamma = (T)a.gamma;
@@ -338,14 +349,14 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
 
             // ---- ring pass: the one face state of each ring cell the
             //      interior reads, and its eta J
-            if (kI && isring) {
+            if (kI && wv == (k & 3)) {
                 T ur[NV], urm[NV], urp[NV];
                 const T *rn = rplane(k + 1);
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    ur[v] = sc[v * XS3 + xq];
-                    urm[v] = sm[v * XS3 + xq];
-                    urp[v] = rn[v * NRING + ri];
+                    ur[v] = sc[v * XS3 + xqr];
+                    urm[v] = sm[v * XS3 + xqr];
+                    urp[v] = rn[v * NRING + rir];
                 }
                 // left state of the face -1/2 (ring at -1) or right state of
                 // the face NB-1/2 (ring at NB); a state with rho <= 0 or
@@ -354,21 +365,21 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                 Prim<T> ws;
                 if constexpr (SCH == SCH_LF) {
                     T dl[3][NV];
-                    slopes(sc, xq, ur, urm, urp, dl);
+                    slopes(sc, xqr, ur, urm, urp, dl);
                     predict(ur, dl, ut);
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
-                        const T dv = rdim == 0 ? dl[0][v] : dl[1][v];
-                        S[v] = rlo ? ut[v] + T(0.5) * dv : ut[v] - T(0.5) * dv;
+                        const T dv = rdr == 0 ? dl[0][v] : dl[1][v];
+                        S[v] = rlr ? ut[v] + T(0.5) * dv : ut[v] - T(0.5) * dv;
                     }
                 } else {
-                    const int st = rdim == 0 ? 1 : SY;
+                    const int st = rdr == 0 ? 1 : SY;
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
                         const T *row = sc + v * XS3;
                         T L, R;
-                        weno_pair(row[xq - st], ur[v], row[xq + st], L, R);
-                        S[v] = rlo ? L : R;
+                        weno_pair(row[xqr - st], ur[v], row[xqr + st], L, R);
+                        S[v] = rlr ? L : R;
                         ut[v] = ur[v];
                     }
                 }
@@ -382,14 +393,14 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                 }
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    srf[(rdim * NV + v) * XS3 + xq] = S[v];
-                spr[rdim * XS3 + xq] = ws.p;
+                    srf[(rdr * NV + v) * XS3 + xqr] = S[v];
+                spr[rdr * XS3 + xqr] = ws.p;
                 if constexpr (RESIST) {
                     T e[5], qz;
-                    curl(sc, xq, ur, urm, urp, e, qz);
+                    curl(sc, xqr, ur, urm, urp, e, qz);
 #pragma unroll
                     for (int i = 0; i < 5; i++)
-                        sj[i * XS3 + xq] = e[i];
+                        sj[i * XS3 + xqr] = e[i];
                 }
             }
 
