@@ -20,7 +20,9 @@
 //     cells (for LF the predictor, then the one face state the interior
 //     reads) runs on one wave, one lane per cell, the wave taking turns
 //     with the plane index, so that the other three waves issue nothing for
-//     it; lanes 0-15 of the waves of the -1 sides form the flux of that face;
+//     it (for WENO, whose pass is a few face states, on the ring lanes of
+//     every wave); lanes 0-15 of the waves of the -1 sides form the flux of
+//     that face;
 //   * lanes 16-35 of each wave load the remaining cells of the padded plane
 //     (outer ring and ring corners), one plane ahead;
 //   * interior columns read their planes from the block itself or, for the
@@ -114,15 +116,17 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
     // the ring cell is the left state of the face -1/2 (x or y = -1)
     const int rdim = wv >> 1;
     const bool rlo = (wv & 1) == 0;
-    // ring-pass role (every lane of the wave that runs the ring pass of a
-    // plane): ring cell ln, on side ln / 16
+    // ring-pass role.  LF: every lane of the wave that runs the ring pass of
+    // a plane, ring cell ln on side ln / 16.  WENO (whose ring pass is a few
+    // face states, cheaper than moving it): the ring lanes of every wave
+    constexpr bool RING1 = SCH == SCH_LF;
     const int rsd = ln >> 4, rix = ln & 15;
     const int rex = rsd == 0 ? -1 : (rsd == 1 ? NB : rix);
     const int rey = rsd == 2 ? -1 : (rsd == 3 ? NB : rix);
-    const int xqr = (rey + NG) * PD + rex + NG;
-    const int rir = ln;
-    const int rdr = rsd >> 1;
-    const bool rlr = (rsd & 1) == 0;
+    const int xqr = RING1 ? (rey + NG) * PD + rex + NG : xq;
+    const int rir = RING1 ? ln : ri;
+    const int rdr = RING1 ? rsd >> 1 : rdim;
+    const bool rlr = RING1 ? (rsd & 1) == 0 : rlo;
 
     Phys<T, MIXED> ph;
     ph.gamma = (T)a.gamma;
@@ -349,7 +353,7 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
 
             // ---- ring pass: the one face state of each ring cell the
             //      interior reads, and its eta J
-            if (kI && wv == (k & 3)) {
+            if (kI && (RING1 ? wv == (k & 3) : isring)) {
                 T ur[NV], urm[NV], urp[NV];
                 const T *rn = rplane(k + 1);
 #pragma unroll
