@@ -341,6 +341,7 @@ def measure_config(key, precision_b, precision_p, steps_b, steps_p, l1_cycles=0,
     out["batched"] = {"precision": precision_b, "value": cells / tb, "ms_per_step": tb * 1e3,
                       "steps": steps_b, "launch": launch_label(cfg, False),
                       "launch_config": cfg, "flags": [int(c) for c in cnt]}
+    out["roofline"] = config_roofline(wb, sim, precision_b)
     del sim
     torch.cuda.empty_cache()
     if batched_only:
@@ -359,8 +360,21 @@ def measure_config(key, precision_b, precision_p, steps_b, steps_p, l1_cycles=0,
         orc.build(force=False)
         orc.set_threads(host_threads())
         A = orc.load_workload(w64)
+        t0 = time.perf_counter()
         A.run(l1_cycles)
+        tN = time.perf_counter() - t0
+        n1 = max(1, min(l1_cycles, int(2e6 // max(cells, 1)) + 1))
         orc.set_threads(1)
+        A1 = orc.load_workload(w64)
+        t0 = time.perf_counter()
+        A1.run(n1)
+        t1 = time.perf_counter() - t0
+        del A1
+        out["oracle"] = {"kind": "oracle", "unit": "cell-updates/s",
+                         "value": cells * l1_cycles / tN, "cores": host_threads(),
+                         "sample": f"FP64 oracle, {l1_cycles} whole cycles of this configuration",
+                         "one_core": {"value": cells * n1 / t1, "cores": 1,
+                                      "sample": f"FP64 oracle, {n1} whole cycle(s), 1 thread"}}
         q = Simulation(wb, precision=precision_b)
         q.load_initial()
         q.set_launch_config(**{k: v for k, v in cfg.items() if k != "step_blocks_per_group"})
@@ -371,6 +385,29 @@ def measure_config(key, precision_b, precision_p, steps_b, steps_p, l1_cycles=0,
         del q, A
         torch.cuda.empty_cache()
     return out
+
+
+def config_roofline(wl, sim, precision):
+    """The step kernel of a configuration's batched path alone (HIP events on
+    its stream): duration, algorithmic HBM rate and fraction of 8 TB/s, and for
+    LF the algorithmic FLOP rate and fraction of the vector peak (the FLOP
+    count of MMC is not tabulated); `bound` names the roof with the larger
+    fraction."""
+    nleaves = int(wl.leaf_mask().sum())
+    cells = wl.n_leaf_cells()
+    ms = time_step_kernel(sim, 10) * 1e3
+    word = 8 if precision == "fp64" else 4
+    nbytes = step_bytes_per_launch(wl, nleaves, word)
+    gbs = nbytes / ms * 1e-6
+    r = {"kernel_ms": ms, "algorithmic_bytes_per_launch": nbytes, "hbm_achieved_GBs": gbs,
+         "hbm_peak_GBs": HBM_PEAK_GBS, "hbm_frac": gbs / HBM_PEAK_GBS}
+    fpc = FLOPS_PER_CELL.get((wl.ndim, wl.eta > 0)) if wl.scheme == "lf" else None
+    if fpc is not None:
+        tflops = fpc * cells / ms * 1e-9
+        r.update({"flops_per_cell_update": fpc, "alu_achieved_TFLOPs": tflops,
+                  "alu_peak_TFLOPs": ALU_PEAK_TFLOPS, "alu_frac": tflops / ALU_PEAK_TFLOPS})
+    r["bound"] = "alu" if fpc is not None and r["alu_frac"] > r["hbm_frac"] else "hbm"
+    return r
 
 
 # the configurations measured besides the headline: key -> (batched precision,
@@ -771,6 +808,11 @@ def main():
             log(f"  {r['batched']['value'] / 1e9:.3f} G vs {r['plain']['value'] / 1e9:.4f} G "
                 f"cell-updates/s (x{r['speedup_batched_vs_plain']:.0f}); L1 rho "
                 f"{l1.get('rho', float('nan')):.2e}")
+            rf, oc = r["roofline"], r.get("oracle")
+            log(f"  step kernel {rf['kernel_ms']:.3f} ms: HBM {rf['hbm_frac']:.3f}"
+                + (f", ALU {rf['alu_frac']:.3f}" if "alu_frac" in rf else "")
+                + (f"; oracle {oc['value'] / 1e6:.2f} M/s on {oc['cores']} cores, "
+                   f"{oc['one_core']['value'] / 1e6:.2f} M/s on one" if oc else ""))
 
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) and the FP32 path's L1 against it")
