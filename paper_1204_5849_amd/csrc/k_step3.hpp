@@ -353,6 +353,12 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
 
             // ---- ring pass: the one face state of each ring cell the
             //      interior reads, and its eta J
+            // LF: the wave that runs this plane's ring pass has the most work
+            // before the barrier (B); it issues ahead of the other workgroup's
+            // wave on its SIMD until then
+            const bool ringw = RING1 && kI && wv == (k & 3);
+            if (ringw)
+                __builtin_amdgcn_s_setprio(2);
             if (kI && (RING1 ? wv == (k & 3) : isring)) {
                 T ur[NV], urm[NV], urp[NV];
                 const T *rn = rplane(k + 1);
@@ -517,6 +523,8 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                     jc[2] = qz;
                 }
             }
+            if (ringw)
+                __builtin_amdgcn_s_setprio(0);
             __syncthreads();  // (B) face states, their pressures and eta J published
 
             // ---- fluxes: in-plane faces x+1/2, y+1/2 of the interior cells and
