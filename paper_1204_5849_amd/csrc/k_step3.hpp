@@ -528,7 +528,12 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
             __syncthreads();  // (B) face states, their pressures and eta J published
 
             // ---- fluxes: in-plane faces x+1/2, y+1/2 of the interior cells and
-            //      the faces -1/2 (ring waves of the -1 sides)
+            //      the faces -1/2 (ring waves of the -1 sides).  The flux of a
+            //      face replaces the right state it was formed from, in the
+            //      slot of the cell on the face's right: that slot has one
+            //      reader, the lane that forms the flux, so no barrier is
+            //      needed between the reads of the states and the writes of
+            //      the fluxes
             T fin[2][NV];
             T rin[4] = {T(0), T(0), T(0), T(0)};
             if (kI) {
@@ -539,12 +544,18 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                 face_flux<RS, 0>(Lin[0], pLin[0], R, spr[q + 1], gam, ph.gm1, ch, ch2, fin[0]);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
+                    srf[(0 * NV + v) * XS3 + q + 1] = fin[0][v];
+#pragma unroll
+                for (int v = 0; v < NV; v++)
                     R[v] = srf[(1 * NV + v) * XS3 + q + SY];
                 face_flux<RS, 1>(Lin[1], pLin[1], R, spr[XS3 + q + SY], gam, ph.gm1, ch, ch2, fin[1]);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    srf[(1 * NV + v) * XS3 + q + SY] = fin[1][v];
             }
             if (kI && isring && rlo) {
-                // the ring cell's own state is the left one; the flux replaces
-                // it in place (no other lane reads this slot before (D))
+                // the ring cell's own state is the left one, the first
+                // interior cell's the right one
                 const int qn = xq + (rdim == 0 ? 1 : SY);
                 T L[NV], R[NV], f[NV];
 #pragma unroll
@@ -559,7 +570,7 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                     face_flux<RS, 1>(L, pl, R, pr, gam, ph.gm1, ch, ch2, f);
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    srf[(rdim * NV + v) * XS3 + xq] = f[v];
+                    srf[(rdim * NV + v) * XS3 + qn] = f[v];
                 const int fb = a.fbidx[(size_t)slot * 6 + 2 * rdim];
                 if (fb >= 0) {
                     const int tt = (rdim == 0 ? ey : ex) + NB * k;
@@ -579,7 +590,6 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                 }
             }
             const bool dom = k >= 0;
-            __syncthreads();  // (C) all reads of the face states done
             // WENO stage 2: u of the cell finalised in this iteration
             T ubase[SCH == SCH_WENO2 ? NV : 1];
             if constexpr (SCH == SCH_WENO2) {
@@ -591,11 +601,6 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                 }
             }
             if (kI) {
-#pragma unroll
-                for (int d = 0; d < 2; d++)
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        srf[(d * NV + v) * XS3 + q] = fin[d][v];
                 // fluxes of block faces shared with another level (reflux):
                 // the faces NB-1/2 here, the faces -1/2 in the ring pass
 #pragma unroll
@@ -652,8 +657,8 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
             if (kI) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    T acc = dtdx[0] * (fin[0][v] - srf[(0 * NV + v) * XS3 + q - 1]);
-                    acc += dtdx[1] * (fin[1][v] - srf[(1 * NV + v) * XS3 + q - SY]);
+                    T acc = dtdx[0] * (fin[0][v] - srf[(0 * NV + v) * XS3 + q]);
+                    acc += dtdx[1] * (fin[1][v] - srf[(1 * NV + v) * XS3 + q]);
                     Wc[v] = sc[v * XS3 + q] - acc;
                 }
                 if (a.eglm) {
