@@ -395,7 +395,11 @@ __global__ void __launch_bounds__(nt_of(BPW)) k_step2(StepArgs a)
             }
             __syncthreads();  // (B) right face states, their pressures and eta J published
 
-            // ---- fluxes of the x faces of row k
+            // ---- fluxes of the x faces of row k.  The flux of a face replaces
+            //      the right state it was formed from, in the slot of the cell
+            //      on the face's right: that slot has one reader, the lane that
+            //      forms the flux, so no barrier is needed between the reads of
+            //      the states and the writes of the fluxes
             T fin[NV];
             T rin[3] = {T(0), T(0), T(0)};
             const bool dof = kI && lane && qx >= -1 && qx < NB;
@@ -405,6 +409,9 @@ __global__ void __launch_bounds__(nt_of(BPW)) k_step2(StepArgs a)
                 for (int v = 0; v < NV; v++)
                     R[v] = srf[(lb * NV + v) * XS + q + 1];
                 face_flux<RS, 0>(Lin, pLin, R, spr[lb * XS + q + 1], gam, ph.gm1, ch, ch2, fin);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    srf[(lb * NV + v) * XS + q + 1] = fin[v];
             }
             if constexpr (RESIST) {
                 if (inI && kI) {
@@ -416,12 +423,6 @@ __global__ void __launch_bounds__(nt_of(BPW)) k_step2(StepArgs a)
                 }
             }
             const bool dom = inI && k >= 0;
-            __syncthreads();  // (C) all reads of the right face states done
-            if (dof) {
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    srf[(lb * NV + v) * XS + q] = fin[v];
-            }
             // fluxes of block faces shared with another level (reflux)
             if (has) {
                 if (dof && (qx == -1 || qx == NB - 1)) {
@@ -472,7 +473,7 @@ __global__ void __launch_bounds__(nt_of(BPW)) k_step2(StepArgs a)
             if (inI && kI) {
 #pragma unroll
                 for (int v = 0; v < NV; v++) {
-                    const T acc = dtdx[0] * (fin[v] - srf[(lb * NV + v) * XS + q - 1]);
+                    const T acc = dtdx[0] * (fin[v] - srf[(lb * NV + v) * XS + q]);
                     Wc[v] = sc[(lb * NV + v) * XS + q] - acc;
                 }
                 if (a.eglm) {
