@@ -137,8 +137,8 @@ static double fast_speed(const orc_params *p, const double *u, int d)
     return sqrt(cf2);
 }
 
-/* |v_d| + fast magnetosonic speed along d (the "local maximum eigenvalue"
- * of the MHD part; the GLM speed c_h is handled separately). */
+/* |v_d| + fast magnetosonic speed along d: the local largest eigenvalue of
+ * the MHD part (Sec. 3.1-3.2); the GLM speed c_h is handled separately. */
 double orc_speed(const orc_params *p, const double *u, int d)
 {
     if (p->physics == ORC_SCALAR)

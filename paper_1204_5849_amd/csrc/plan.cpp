@@ -1,6 +1,6 @@
 // plan.cpp -- host runtime: block-tree validation, Morton ordering and the
 // tables the kernels read.  This is the single-GPU counterpart of the
-// paper's "neighbour statistics" (Sec. 4.2): everything a step needs to find
+// neighbour statistics of Sec. 4.2: everything a step needs to find
 // its neighbours, parents, children and reflux partners is computed once here.
 #include "plan.hpp"
 

@@ -1,5 +1,5 @@
 // plan.hpp -- host-side context: the validated block tree in Morton order and
-// the tables the kernels read ("neighbour statistics" of the paper, Sec. 4.2).
+// the tables the kernels read (the neighbour statistics of Sec. 4.2).
 #pragma once
 
 #include <string>
