@@ -9,6 +9,11 @@ namespace mapk {
 
 namespace {
 constexpr int NTE = 256;
+// the estimator's workgroup: in 3-D 512 threads per block (8 waves), so that
+// the two blocks whose 64 KB FP64 staging tiles fit in a CU's LDS keep four
+// waves per SIMD over their long FP64 chains (3.91 -> 2.68 ms on the Harris
+// sheet against 256 threads); in 2-D (400 cells) 256
+constexpr int nt_est(int ndim) { return ndim == 3 ? 512 : 256; }
 }
 
 // value of criterion i at a padded cell of block `slot` (read where the
@@ -30,11 +35,12 @@ __device__ __forceinline__ double est_value(const EstArgs &a, int i, int slot, i
 // is formed once per padded cell (ghosts read where the descriptors point)
 // and staged in LDS; the stencil then runs on LDS.
 template <int NDIM, typename T>
-__global__ void __launch_bounds__(NTE) k_estimate(EstArgs a)
+__global__ void __launch_bounds__(nt_est(NDIM)) k_estimate(EstArgs a)
 {
+    constexpr int NTEST = nt_est(NDIM);
     constexpr int PT = tile_cells<NDIM>();
     __shared__ double sv[PT];
-    __shared__ double red[NTE / 64];
+    __shared__ double red[NTEST / 64];
     constexpr int E = NB + 2;
     constexpr int NE = NDIM == 3 ? E * E * E : E * E;
     const int st[3] = {1, PD, PD * PD};
@@ -43,13 +49,13 @@ __global__ void __launch_bounds__(NTE) k_estimate(EstArgs a)
         const double scale = pow(a.est.ratio, a.est.xi * (level - 1));
         double best = 0.0;
         for (int i = 0; i < a.est.ncrit; i++) {
-            for (int c = threadIdx.x; c < PT; c += NTE) {
+            for (int c = threadIdx.x; c < PT; c += NTEST) {
                 const int x = c % PD - NG, y = (c / PD) % PD - NG;
                 const int z = NDIM == 3 ? c / (PD * PD) - NG : 0;
                 sv[c] = est_value<NDIM, T>(a, i, slot, x, y, z);
             }
             __syncthreads();
-            for (int e = threadIdx.x; e < NE; e += NTE) {
+            for (int e = threadIdx.x; e < NE; e += NTEST) {
                 const int x = e % E - 1, y = (e / E) % E - 1, z = NDIM == 3 ? e / (E * E) - 1 : 0;
                 const int c = lin<NDIM>(x, y, z);
                 const double v = sv[c];
@@ -79,7 +85,7 @@ __global__ void __launch_bounds__(NTE) k_estimate(EstArgs a)
         __syncthreads();
         if (threadIdx.x == 0) {
             double r = red[0];
-            for (int w = 1; w < NTE / 64; w++)
+            for (int w = 1; w < NTEST / 64; w++)
                 r = red[w] > r ? red[w] : r;
             a.err[slot] = r;
         }
@@ -108,14 +114,14 @@ hipError_t launch_estimate(int ndim, bool fp64, const EstArgs &a, hipStream_t s)
         return hipSuccess;
     if (ndim == 2) {
         if (fp64)
-            hipLaunchKernelGGL((k_estimate<2, double>), dim3(a.nslots), dim3(NTE), 0, s, a);
+            hipLaunchKernelGGL((k_estimate<2, double>), dim3(a.nslots), dim3(nt_est(2)), 0, s, a);
         else
-            hipLaunchKernelGGL((k_estimate<2, float>), dim3(a.nslots), dim3(NTE), 0, s, a);
+            hipLaunchKernelGGL((k_estimate<2, float>), dim3(a.nslots), dim3(nt_est(2)), 0, s, a);
     } else {
         if (fp64)
-            hipLaunchKernelGGL((k_estimate<3, double>), dim3(a.nslots), dim3(NTE), 0, s, a);
+            hipLaunchKernelGGL((k_estimate<3, double>), dim3(a.nslots), dim3(nt_est(3)), 0, s, a);
         else
-            hipLaunchKernelGGL((k_estimate<3, float>), dim3(a.nslots), dim3(NTE), 0, s, a);
+            hipLaunchKernelGGL((k_estimate<3, float>), dim3(a.nslots), dim3(nt_est(3)), 0, s, a);
     }
     return hipGetLastError();
 }
