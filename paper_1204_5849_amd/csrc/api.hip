@@ -9,10 +9,10 @@
 #include <cstring>
 #include <mutex>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "kernels.hpp"
+#include "keymap.hpp"
 #include "plan.hpp"
 
 using namespace mapk;
@@ -1055,24 +1055,23 @@ map_status map_remap(map_ctx *dst, void *Ud, const map_ctx *src, const void *Us,
         src->sims.size() != dst->sims.size() ||
         std::memcmp(src->sims.data(), dst->sims.data(), sizeof(map_sim_desc) * src->sims.size()))
         return fail(MAP_EINVAL, "contexts differ in dimension, precision or simulations");
-    std::unordered_map<uint64_t, int> src_slot;
-    src_slot.reserve((size_t)src->nslots * 2);
+    KeyMap src_slot(src->nslots);
     auto pack = [](const map_block_key &k) {
         return ((uint64_t)k.sim << 47) | ((uint64_t)k.level << 42) | ((uint64_t)k.ix << 28) |
                ((uint64_t)k.iy << 14) | (uint64_t)k.iz;
     };
     for (int s = 0; s < src->nslots; s++)
-        src_slot[pack(src->key[s])] = s;
+        src_slot.insert(pack(src->key[s]), s);
     dst->remap_src.assign(dst->nslots, -1);
     dst->remap_new.clear();
     for (int s = 0; s < dst->nslots; s++) {
-        auto it = src_slot.find(pack(dst->key[s]));
-        if (it != src_slot.end()) {
-            dst->remap_src[s] = it->second;
+        const int from = src_slot.find(pack(dst->key[s]));
+        if (from >= 0) {
+            dst->remap_src[s] = from;
             continue;
         }
         const int p = dst->parent[s];
-        if (p < 0 || !src_slot.count(pack(dst->key[p])))
+        if (p < 0 || !src_slot.contains(pack(dst->key[p])))
             return fail(MAP_ETREE, "a new block's parent is not in the source tree");
         dst->remap_new.push_back(s);
     }

@@ -2,13 +2,13 @@
 // tables the kernels read.  This is the single-GPU counterpart of the
 // neighbour statistics of Sec. 4.2: everything a step needs to find
 // its neighbours, parents, children and reflux partners is computed once here.
+#include "keymap.hpp"
 #include "plan.hpp"
 
 #include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstring>
-#include <unordered_map>
 
 using namespace mapk;
 
@@ -35,12 +35,8 @@ uint64_t pack(int sim, int level, int ix, int iy, int iz)
 }
 
 struct Tree {
-    std::unordered_map<uint64_t, int> slot;
-    int find(int s, int l, int x, int y, int z) const
-    {
-        auto it = slot.find(pack(s, l, x, y, z));
-        return it == slot.end() ? -1 : it->second;
-    }
+    mapk::KeyMap slot;
+    int find(int s, int l, int x, int y, int z) const { return slot.find(pack(s, l, x, y, z)); }
 };
 
 int blocks_at(const map_sim_desc &s, int d, int level) { return s.nbase[d] << (level - 1); }
@@ -137,6 +133,7 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
 
     // ---- keys: range checks and duplicates
     Tree input;
+    input.slot.reserve(nblocks);
     int lmax = 1;
     for (int i = 0; i < nblocks; i++) {
         const map_block_key &k = keys[i];
@@ -154,7 +151,7 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
             }
         }
         uint64_t pk = pack(k.sim, k.level, k.ix, k.iy, k.iz);
-        if (!input.slot.emplace(pk, i).second) {
+        if (!input.slot.insert(pk, i)) {
             err = "key " + std::to_string(i) + ": duplicate block";
             return MAP_ETREE;
         }
@@ -243,10 +240,11 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
     c->slot_of_key.assign(n, -1);
     c->key.resize(n);
     Tree tr;
+    tr.slot.reserve(n);
     for (int s = 0; s < n; s++) {
         c->slot_of_key[order[s]] = s;
         c->key[s] = keys[order[s]];
-        tr.slot.emplace(pack(c->key[s].sim, c->key[s].level, c->key[s].ix, c->key[s].iy, c->key[s].iz), s);
+        tr.slot.insert(pack(c->key[s].sim, c->key[s].level, c->key[s].ix, c->key[s].iy, c->key[s].iz), s);
     }
 
     // ---- parent / children / leaves

@@ -5,10 +5,9 @@
 #include <cmath>
 #include <cstring>
 #include <string>
-#include <unordered_map>
-#include <unordered_set>
 #include <vector>
 
+#include "keymap.hpp"
 #include "plan.hpp"
 
 using namespace mapk;
@@ -51,11 +50,10 @@ extern "C" map_status map_regrid(const map_ctx *c, const double *err, const map_
         return regrid_fail(MAP_EINVAL, "max_level out of range");
     const int n = c->nslots, nd = c->nd;
     const int nkids = 1 << nd;
-    std::unordered_map<uint64_t, int> slot_of;
-    slot_of.reserve((size_t)n * 2);
+    KeyMap slot_of(n);
     for (int s = 0; s < n; s++) {
         const map_block_key &k = c->key[s];
-        slot_of[pack(k.sim, k.level, k.ix, k.iy, k.iz)] = s;
+        slot_of.insert(pack(k.sim, k.level, k.ix, k.iy, k.iz), s);
     }
     auto kids_of = [&](int s) {
         const map_block_key &k = c->key[s];
@@ -83,7 +81,7 @@ extern "C" map_status map_regrid(const map_ctx *c, const double *err, const map_
     }
 
     // closure: a new leaf must not touch a leaf two or more levels coarser
-    std::unordered_set<uint64_t> leaves;
+    KeyMap leaves(n * nkids);
     for (;;) {
         leaves.clear();
         for (int s = 0; s < n; s++) {
@@ -94,15 +92,15 @@ extern "C" map_status map_regrid(const map_ctx *c, const double *err, const map_
                     continue;
                 if (refine[s]) {
                     for (uint64_t ch : kids_of(s))
-                        leaves.insert(ch);
+                        leaves.insert(ch, 0);
                 } else {
-                    leaves.insert(pack(k.sim, k.level, k.ix, k.iy, k.iz));
+                    leaves.insert(pack(k.sim, k.level, k.ix, k.iy, k.iz), 0);
                 }
             } else if (coarsen[s]) {
-                leaves.insert(pack(k.sim, k.level, k.ix, k.iy, k.iz));
+                leaves.insert(pack(k.sim, k.level, k.ix, k.iy, k.iz), 0);
             }
         }
-        std::vector<uint64_t> order(leaves.begin(), leaves.end());
+        std::vector<uint64_t> order(leaves.keys());
         std::sort(order.begin(), order.end());
         bool changed = false;
         for (uint64_t a : order) {
@@ -134,13 +132,12 @@ extern "C" map_status map_regrid(const map_ctx *c, const double *err, const map_
                         for (int bl = ka.level - 1; bl >= 1; bl--) {
                             const int sh = ka.level - bl;
                             const uint64_t b = pack(ka.sim, bl, nc[0] >> sh, nc[1] >> sh, nc[2] >> sh);
-                            if (!leaves.count(b))
+                            if (!leaves.contains(b))
                                 continue;
                             if (bl <= ka.level - 2) {
-                                auto it = slot_of.find(b);
-                                if (it == slot_of.end())
+                                const int sb = slot_of.find(b);
+                                if (sb < 0)
                                     return regrid_fail(MAP_ETREE, "input tree is not 2:1 balanced");
-                                const int sb = it->second;
                                 if (coarsen[sb]) {
                                     coarsen[sb] = 0;
                                 } else {
@@ -160,16 +157,18 @@ extern "C" map_status map_regrid(const map_ctx *c, const double *err, const map_
     }
 
     // the new tree: the new leaves and all their ancestors
-    std::unordered_set<uint64_t> all(leaves.begin(), leaves.end());
-    for (uint64_t k : leaves)
+    KeyMap all(2 * leaves.size());
+    for (uint64_t k : leaves.keys())
+        all.insert(k, 0);
+    for (uint64_t k : leaves.keys())
         for (uint64_t a = k; unpack(a).level > 1;) {
             a = parent_of(a);
-            if (!all.insert(a).second)
+            if (!all.insert(a, 0))
                 break;
         }
     std::vector<map_block_key> out;
     out.reserve(all.size());
-    for (uint64_t k : all)
+    for (uint64_t k : all.keys())
         out.push_back(unpack(k));
     std::sort(out.begin(), out.end(), [](const map_block_key &x, const map_block_key &y) {
         if (x.sim != y.sim)
