@@ -384,7 +384,7 @@ def measure_config(key, precision_b, precision_p, steps_b, steps_p, l1_cycles=0,
                                       "sample": f"FP64 oracle, {n1} whole cycle(s), 1 thread"}}
         q = Simulation(wb, precision=precision_b)
         q.load_initial()
-        q.set_launch_config(**{k: v for k, v in cfg.items() if k != "step_blocks_per_group"})
+        q.set_launch_config(**cfg)
         q.graph_run(l1_cycles)
         q.sync()
         out["rel_l1_vs_oracle"] = {"cycles": l1_cycles, "precision": precision_b,

@@ -214,17 +214,30 @@ map_status run_cfl(map_ctx *c, const void *U, map_dt *dt_out, hipStream_t s,
 
 // after a restriction that formed the parts of every leaf with a parent:
 // the parts of the leaves without one, then the dt records into dt_int
+// whether the 2-D LF update forms the next cycle's CFL maxima of the leaves
+// without parent that no reflux changes (map_launch::cfl_in_update)
+bool cfl_in_update(const map_ctx *c)
+{
+    if (c->nd != 2 || c->p.scheme != MAP_LF)
+        return false;
+    return c->cfl_in_update > 0 || (c->cfl_in_update < 0 && c->nleaves >= 4 * c->ncu);
+}
+
+// the CFL maxima of the leaves without parent that neither the restriction
+// nor the update formed, then the dt records
 map_status run_cfl_rest(map_ctx *c, const void *U, hipStream_t s, map_dt *dt_int)
 {
-    if (!c->orphans.empty()) {
+    const bool fused = cfl_in_update(c);
+    const size_t n = fused ? c->orphans_rest.size() : c->orphans.size();
+    if (n > 0) {
         CflArgs a{};
         a.U = U;
         a.cnt = dptr<unsigned long long>(c, c->ws.counters);
         a.gamma = c->p.gamma;
-        a.leaves = dptr<int32_t>(c, c->ws.orphans);
-        a.nleaves = (int)c->orphans.size();
+        a.leaves = dptr<int32_t>(c, fused ? c->ws.orphans_rest : c->ws.orphans);
+        a.nleaves = (int)n;
         a.part = dptr<double>(c, c->ws.cfl_part);
-        a.part_idx = dptr<int32_t>(c, c->ws.orphan_idx);
+        a.part_idx = dptr<int32_t>(c, fused ? c->ws.orphan_rest_idx : c->ws.orphan_idx);
         HIPCHK(launch_cfl(c->nd, fp64(c), a, s));
     }
     return run_dt(c, nullptr, s, dt_int);
@@ -232,7 +245,7 @@ map_status run_cfl_rest(map_ctx *c, const void *U, hipStream_t s, map_dt *dt_int
 
 // one launch of the block-update kernel of the scheme (for WENO: one stage)
 map_status run_step_kernel(map_ctx *c, int sch, const void *Uin, void *Uout, const void *Ubase,
-                           const map_dt *dt, hipStream_t s)
+                           const map_dt *dt, hipStream_t s, bool cfl_next = false)
 {
     StepArgs a{};
     a.Uin = Uin;
@@ -251,6 +264,9 @@ map_status run_step_kernel(map_ctx *c, int sch, const void *Uin, void *Uout, con
     a.limiter = c->p.limiter;
     a.riemann = c->p.riemann;
     a.shape = c->step_shape;
+    a.cfl_on = cfl_next && cfl_in_update(c);
+    a.cfl_leaf = dptr<int32_t>(c, c->ws.cfl_leaf);
+    a.cfl_part = dptr<double>(c, c->ws.cfl_part);
     const bool resist = c->p.eta > 0.0;
     auto launch = [&](const StepArgs &x, int grid) -> hipError_t {
         if (c->p.scheme == MAP_MMC)
@@ -282,10 +298,11 @@ void *shadow(map_ctx *c);
 // the shadow state, restriction and the ghosts the next stage reads from a
 // block's own tile on it, stage 2 from the shadow with u^n = Uin; Uout may
 // be Uin (stage 2 reads u^n only at the cell it writes)
-map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, hipStream_t s)
+map_status run_step(map_ctx *c, const void *Uin, void *Uout, const map_dt *dt, hipStream_t s,
+                    bool cfl_next = false)
 {
     if (c->p.scheme != MAP_WENO)
-        return run_step_kernel(c, SCH_LF, Uin, Uout, nullptr, dt, s);
+        return run_step_kernel(c, SCH_LF, Uin, Uout, nullptr, dt, s, cfl_next);
     map_status st;
     void *S1 = shadow(c);
     if ((st = run_step_kernel(c, SCH_WENO1, Uin, S1, nullptr, dt, s)) != MAP_OK)
@@ -369,14 +386,15 @@ map_status run_conduct(map_ctx *c, void *U, void *scratch, const map_dt *dt, hip
 // shadow when the cycle runs in place).  With `next`, the next cycle's dt
 // records are formed into `next` on the way: the restriction takes the CFL
 // maxima of the leaves with a parent from the values it reads (final after
-// reflux), a small pass those of the leaves without one.
+// reflux), the 2-D LF update those of the leaves without one that no reflux
+// changes (from the values it writes), a small pass the rest.
 map_status run_cycle(map_ctx *c, const void *Uin, void *Uout, hipStream_t s, map_dt *dt,
                      bool need_cfl, map_dt *next)
 {
     map_status st;
     if (need_cfl && (st = run_cfl(c, Uin, nullptr, s, dt)) != MAP_OK)
         return st;
-    if ((st = run_step(c, Uin, Uout, dt, s)) != MAP_OK)
+    if ((st = run_step(c, Uin, Uout, dt, s, next != nullptr)) != MAP_OK)
         return st;
     if ((st = run_reflux(c, Uout, dt, s)) != MAP_OK)
         return st;
@@ -572,6 +590,10 @@ map_status map_bind_workspace(map_ctx *c, void *ws, size_t bytes, void *stream)
     HIPCHK(up(c->ws.leaf_of, c->leaf_of.data(), c->leaf_of.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.orphans, c->orphans.data(), c->orphans.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.orphan_idx, c->orphan_idx.data(), c->orphan_idx.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.cfl_leaf, c->cfl_leaf.data(), c->cfl_leaf.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.orphans_rest, c->orphans_rest.data(), c->orphans_rest.size() * sizeof(int32_t)));
+    HIPCHK(up(c->ws.orphan_rest_idx, c->orphan_rest_idx.data(),
+              c->orphan_rest_idx.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.restrict_list, c->restrict_list.data(), c->restrict_list.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.prolong_list, c->prolong_list.data(), c->prolong_list.size() * sizeof(int32_t)));
     HIPCHK(up(c->ws.prolong_mask, c->prolong_mask.data(), c->prolong_mask.size() * sizeof(uint32_t)));
@@ -894,6 +916,8 @@ map_status map_get_launch(const map_ctx *c, map_launch *out)
     out->step_shape = c->step_shape;
     out->restrict_split = c->restrict_split >= 0 ? c->restrict_split : c->ncu;
     out->step_blocks_per_group = step_blocks_per_group(c->nd, c->p.scheme, c->step_shape);
+    out->cfl_in_update = c->cfl_in_update;
+    out->cfl_in_update_on = cfl_in_update(c) ? 1 : 0;
     return MAP_OK;
 }
 
@@ -905,11 +929,14 @@ map_status map_set_launch_config(map_ctx *c, const map_launch *in)
         return fail(MAP_EINVAL, "step_shape 1 exists for 2-D LF/WENO and 3-D FP32 LF/WENO only");
     if (in->restrict_split < -1)
         return fail(MAP_EINVAL, "restrict_split below -1");
+    if (in->cfl_in_update < -1 || in->cfl_in_update > 1)
+        return fail(MAP_EINVAL, "cfl_in_update must be -1, 0 or 1");
     map_status st = map_set_launch(c, in->mode, in->grid_step, in->grid_fill);
     if (st)
         return st;
     c->step_shape = in->step_shape;
     c->restrict_split = in->restrict_split;
+    c->cfl_in_update = in->cfl_in_update;
     return MAP_OK;
 }
 

@@ -28,6 +28,7 @@
 // A persistent grid strides over the leaf list.
 #include <type_traits>
 
+#include "cfl.hpp"
 #include "kernels.hpp"
 #include "physics.hpp"
 #include "step_common.hpp"
@@ -67,6 +68,9 @@ __global__ void __launch_bounds__(nt_of(BPW), occ_hint<T>(BPW)) k_step2(StepArgs
     // element offsets from Uin (the loads stay in the global address space)
     __shared__ size_t gcol[5 * NT2];
     __shared__ size_t gxc[5 * NXT2];
+    // LF with cfl_on: the next cycle's CFL maximum of each block, as the bits
+    // of a non-negative double (they order like the values)
+    __shared__ unsigned long long scfl[SCH == SCH_LF ? BPW : 1];
 
     // ---- this thread's column and its extra (load-only) cell
     const int t = threadIdx.x;
@@ -128,6 +132,17 @@ __global__ void __launch_bounds__(nt_of(BPW), occ_hint<T>(BPW)) k_step2(StepArgs
         const T dt = (T)rec.dt, ch = (T)rec.ch, ch2 = (T)(rec.ch * rec.ch), damp = (T)rec.damp;
         const T eta = (T)a.eta;
         T *ob = Uout + (size_t)slot * NV * P;
+        // LF with cfl_on: this block's leaf index when the update forms its
+        // next CFL maximum (the values below are final for this cycle), -1
+        // otherwise; the running maximum and the counts of the cells the
+        // CFL pass would count
+        const int cfl_l = SCH == SCH_LF && a.cfl_on && has ? a.cfl_leaf[slot] : -1;
+        double cfl_m = 0.0;
+        unsigned cfl_bad = 0, cfl_nonfin = 0;
+        if constexpr (SCH == SCH_LF) {
+            if (a.cfl_on && t < BPW)
+                scfl[t] = 0ull;
+        }
 
         auto set_src = [&](size_t *tab, int ts, int sl, int cx) {
             const int yr[5] = {-2, -1, 0, NB, NB + 1};
@@ -473,6 +488,25 @@ __global__ void __launch_bounds__(nt_of(BPW), occ_hint<T>(BPW)) k_step2(StepArgs
 #pragma unroll
                 for (int v = 0; v < NV; v++)
                     ob[v * P + (k - 1 + NG) * XS + q] = o[v];
+                if (cfl_l >= 0) {
+                    double u[NV];
+                    bool fin = true;
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        u[v] = (double)o[v];
+                        fin = fin && isfinite(u[v]);
+                    }
+                    if (!fin) {
+                        cfl_nonfin++;
+                    } else {
+                        double pr;
+                        bool b;
+                        const double sp = cfl_speed<2>(u, a.gamma, pr, b);
+                        if (b)
+                            cfl_bad++;
+                        cfl_m = sp > cfl_m ? sp : cfl_m;
+                    }
+                }
             }
             // ---- start row k: x flux difference, EGLM sources and x
             //      resistive terms
@@ -507,6 +541,28 @@ __global__ void __launch_bounds__(nt_of(BPW), occ_hint<T>(BPW)) k_step2(StepArgs
             for (int i = 0; i < 3; i++) {
                 jm2[i] = jm1[i];
                 jm1[i] = jc[i];
+            }
+        }
+        if constexpr (SCH == SCH_LF) {
+            if (a.cfl_on) {
+                // the block's maximum over its columns, then one lane per
+                // block writes it where the CFL pass would
+                if (cfl_l >= 0 && inI) {
+                    atomicMax(&scfl[lb], (unsigned long long)__double_as_longlong(cfl_m));
+                    if (cfl_bad)
+                        atomicAdd(&a.cnt[2], (unsigned long long)cfl_bad);
+                    if (cfl_nonfin)
+                        atomicAdd(&a.cnt[3], (unsigned long long)cfl_nonfin);
+                }
+                __syncthreads();
+                if (t < BPW) {
+                    const int lj = item * BPW + t;
+                    if (lj < a.nleaves) {
+                        const int cl = a.cfl_leaf[a.leaves[lj]];
+                        if (cl >= 0)
+                            a.cfl_part[cl] = __longlong_as_double((long long)scfl[t]);
+                    }
+                }
             }
         }
         __syncthreads();  // LDS reuse by the next work item

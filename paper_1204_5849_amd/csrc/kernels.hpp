@@ -33,6 +33,12 @@ struct StepArgs {
     // 1 = 7 blocks in 2 waves; 3-D FP32 LF / WENO, 0 = compiled for two
     // workgroups per CU (256 registers per lane), 1 = for one (512)
     int shape;
+    // 2-D LF: with cfl_on, the next cycle's CFL maximum of each leaf whose
+    // cfl_leaf[slot] >= 0 (a leaf without parent that no reflux changes) is
+    // formed from the values the update writes, into cfl_part[cfl_leaf[slot]]
+    int cfl_on;
+    const int32_t *cfl_leaf;
+    double *cfl_part;
 };
 
 // energy-only passes of a conduction sub-step (eonly = 1): only the energy

@@ -54,7 +54,8 @@ struct SimRec {
 
 // byte offsets of the tables inside the caller's workspace
 struct WsLayout {
-    size_t blocks, desc, parent, children, fbidx, leaves, leaf_of, orphans, orphan_idx,
+    size_t blocks, desc, parent, children, fbidx, leaves, leaf_of, orphans, orphan_idx, cfl_leaf,
+        orphans_rest, orphan_rest_idx,
         restrict_list, prolong_list, prolong_mask, frame_list, frame_sel, reflux_slots, reflux_start, reflux_recs, sims,
         lvl_dx, dt, dt2, cfl_part,
         cond_part, tot_part, counters, fbuf, remap, newlist, shadow, total;

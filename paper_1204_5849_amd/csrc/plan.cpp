@@ -514,6 +514,28 @@ map_status map_plan_build(map_ctx *c, const map_params *p, int nsims, const map_
         }
     }
     c->reflux_start.push_back((int)c->reflux_recs.size());
+
+    // ---- leaves without parent whose next-cycle CFL maximum the 2-D LF
+    //      update forms as it writes them (reflux would change them after
+    //      the update, so leaves with reflux faces stay with the CFL pass)
+    c->cfl_leaf.assign(n, -1);
+    c->orphans_rest.clear();
+    c->orphan_rest_idx.clear();
+    {
+        std::vector<char> refl(n, 0);
+        for (int s : c->reflux_slots)
+            refl[s] = 1;
+        const bool can = nd == 2 && p->scheme == MAP_LF;
+        for (size_t i = 0; i < c->orphans.size(); i++) {
+            const int s = c->orphans[i];
+            if (can && !refl[s]) {
+                c->cfl_leaf[s] = c->orphan_idx[i];
+            } else {
+                c->orphans_rest.push_back(s);
+                c->orphan_rest_idx.push_back(c->orphan_idx[i]);
+            }
+        }
+    }
     map_plan_layout(c);
     return MAP_OK;
 }
@@ -537,6 +559,9 @@ void map_plan_layout(map_ctx *c)
     L.leaf_of = take(n * sizeof(int32_t));
     L.orphans = take(c->orphans.size() * sizeof(int32_t));
     L.orphan_idx = take(c->orphan_idx.size() * sizeof(int32_t));
+    L.cfl_leaf = take(n * sizeof(int32_t));
+    L.orphans_rest = take(c->orphans_rest.size() * sizeof(int32_t));
+    L.orphan_rest_idx = take(c->orphan_rest_idx.size() * sizeof(int32_t));
     L.restrict_list = take(c->restrict_list.size() * sizeof(int32_t));
     L.prolong_list = take(c->prolong_list.size() * sizeof(int32_t));
     L.prolong_mask = take(c->prolong_mask.size() * sizeof(uint32_t));

@@ -24,6 +24,11 @@ struct map_ctx {
     std::vector<int32_t> leaf_of;          // by slot: index in `leaves`, -1 for parents
     std::vector<int32_t> orphans;          // leaves without a parent (level 1), and
     std::vector<int32_t> orphan_idx;       // their indices in `leaves`
+    std::vector<int32_t> cfl_leaf;         // by slot: index in `leaves` of a leaf without
+                                           // parent whose next CFL maximum the 2-D LF
+                                           // update can form (no reflux after it), else -1
+    std::vector<int32_t> orphans_rest;     // the other leaves without parent, and their
+    std::vector<int32_t> orphan_rest_idx;  // indices in `leaves`
     std::vector<mapk::SimRec> simrec;
     std::vector<double> lvl_dx;            // [sim][MAXL + 1][3]
     std::vector<int32_t> restrict_list;    // parent slots, grouped by level
@@ -52,6 +57,7 @@ struct map_ctx {
     int grid_step = 0, grid_fill = 0;
     int step_shape = 0;        // workgroup shape of the update (StepArgs::shape)
     int restrict_split = -1;   // levels with fewer parents take one workgroup per child (-1: ncu)
+    int cfl_in_update = -1;    // map_launch::cfl_in_update
     int ncu = 256;  // compute units of the bound device
 
     // map_remap: by slot, the source slot in the previous tree (-1: new

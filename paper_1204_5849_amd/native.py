@@ -85,7 +85,8 @@ class map_sizes(C.Structure):
 class map_launch(C.Structure):
     _fields_ = [("mode", C.c_int), ("grid_step", C.c_int), ("grid_fill", C.c_int),
                 ("step_shape", C.c_int), ("restrict_split", C.c_int),
-                ("step_blocks_per_group", C.c_int)]
+                ("step_blocks_per_group", C.c_int), ("cfl_in_update", C.c_int),
+                ("cfl_in_update_on", C.c_int)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -323,10 +324,16 @@ def map_get_launch(ctx) -> dict:
     return out.as_dict()
 
 
+# map_launch fields that map_get_launch reports and map_set_launch_config ignores
+LAUNCH_READ_ONLY = ("step_blocks_per_group", "cfl_in_update_on")
+
+
 def map_set_launch_config(ctx, cfg: dict):
+    """Set the launch settings named in `cfg`, keeping the others (read-only
+    fields in `cfg` are ignored)."""
     x = map_launch()
     cur = map_get_launch(ctx)
-    cur.update(cfg)
+    cur.update({k: v for k, v in cfg.items() if k not in LAUNCH_READ_ONLY})
     for k, _ in map_launch._fields_:
         setattr(x, k, int(cur[k]))
     check(lib().map_set_launch_config(ctx, C.byref(x)))

@@ -219,8 +219,7 @@ class Simulation:
         self._plan(dataclasses.replace(self.wl, keys=keys))
         self._ubuf, self._wsbuf = ubuf, wsbuf
         self._bind()
-        N.map_set_launch_config(self.ctx, {k: v for k, v in cfg.items()
-                                           if k != "step_blocks_per_group"})
+        N.map_set_launch_config(self.ctx, cfg)
         N.map_remap(self.ctx, self.U, old_ctx, old_U, self.sp)  # synchronises the stream
         N.map_destroy(old_ctx)
         self._spare = old_bufs

@@ -303,6 +303,15 @@ def test_launch_config_checks():
                     N.map_set_launch_config(ctx, {"step_shape": 1})
             with pytest.raises(N.MapError):
                 N.map_set_launch_config(ctx, {"restrict_split": -2})
+            with pytest.raises(N.MapError):
+                N.map_set_launch_config(ctx, {"cfl_in_update": 2})
+            # the update forms CFL maxima only in 2-D LF, and by default only
+            # on trees of at least 4 leaves per CU
+            assert cfg["cfl_in_update"] == -1 and cfg["cfl_in_update_on"] == 0
+            N.map_set_launch_config(ctx, {"cfl_in_update": 1, "cfl_in_update_on": 0})
+            got = N.map_get_launch(ctx)
+            assert got["cfl_in_update"] == 1
+            assert got["cfl_in_update_on"] == int(p.ndim == 2 and p.scheme == N.MAP_LF)
         finally:
             N.map_destroy(ctx)
     ctx = N.map_init_blocks(N.make_params(2), w2.sims, w2.keys)

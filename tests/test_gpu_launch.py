@@ -28,7 +28,9 @@ def dev():
 
 
 CONFIGS = [dict(step_shape=1), dict(grid_step=256, grid_fill=256), dict(restrict_split=0),
-           dict(restrict_split=1 << 30), dict(step_shape=1, grid_step=512, restrict_split=64)]
+           dict(restrict_split=1 << 30), dict(step_shape=1, grid_step=512, restrict_split=64),
+           dict(cfl_in_update=1), dict(cfl_in_update=1, step_shape=1, grid_step=256),
+           dict(cfl_in_update=0)]
 
 
 @pytest.mark.parametrize("ndim,scheme,precision", [(2, "lf", "fp64"), (2, "weno", "fp32"),
