@@ -320,6 +320,18 @@ def test_launch_config_checks():
         assert N.map_get_launch(ctx)["step_blocks_per_group"] == 7
     finally:
         N.map_destroy(ctx)
+    # a 2-D LF tree of at least 4 leaves per CU takes the CFL maxima in the
+    # update by default; 0 turns it off, and -1 restores the rule
+    wk = W.kh_ensemble(nsims=64)
+    ctx = N.map_init_blocks(N.make_params(2), wk.sims, wk.keys)
+    try:
+        assert N.map_get_launch(ctx)["cfl_in_update_on"] == 1
+        N.map_set_launch_config(ctx, {"cfl_in_update": 0})
+        assert N.map_get_launch(ctx)["cfl_in_update_on"] == 0
+        N.map_set_launch_config(ctx, {"cfl_in_update": -1})
+        assert N.map_get_launch(ctx)["cfl_in_update_on"] == 1
+    finally:
+        N.map_destroy(ctx)
 
 
 def test_regrid_interval_formula():
