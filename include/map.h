@@ -310,12 +310,13 @@ typedef struct {
     int cfl_in_update;   /* 2-D LF: whether the update forms the next cycle's
                             CFL maxima of the leaves without parent that no
                             reflux changes, in place of the CFL pass over them
-                            (the same dt records bit for bit): -1 = when the
-                            tree has at least 4 leaves per CU (a small tree's
-                            update is latency-bound and the pass runs beside
-                            nothing), 0 = never, 1 = always */
+                            (the same dt records bit for bit): -1 = in batched
+                            launches over at least 4 leaves per CU (a small
+                            tree's update, or a single block's, is
+                            latency-bound and the pass costs little), 0 =
+                            never, 1 = always */
     int cfl_in_update_on;  /* read only: 1 when cfl_in_update is in effect for
-                              this tree, else 0 */
+                              this tree and launch mode, else 0 */
 } map_launch;
 
 map_status map_get_launch(const map_ctx *ctx, map_launch *out);

@@ -215,12 +215,16 @@ map_status run_cfl(map_ctx *c, const void *U, map_dt *dt_out, hipStream_t s,
 // after a restriction that formed the parts of every leaf with a parent:
 // the parts of the leaves without one, then the dt records into dt_int
 // whether the 2-D LF update forms the next cycle's CFL maxima of the leaves
-// without parent that no reflux changes (map_launch::cfl_in_update)
+// without parent that no reflux changes (map_launch::cfl_in_update); the
+// automatic rule takes batched launches over at least 4 leaves per CU (a
+// launch per block runs each update alone, latency-bound)
 bool cfl_in_update(const map_ctx *c)
 {
     if (c->nd != 2 || c->p.scheme != MAP_LF)
         return false;
-    return c->cfl_in_update > 0 || (c->cfl_in_update < 0 && c->nleaves >= 4 * c->ncu);
+    if (c->cfl_in_update >= 0)
+        return c->cfl_in_update == 1;
+    return c->launch_mode == MAP_LAUNCH_BATCHED && c->nleaves >= 4 * c->ncu;
 }
 
 // the CFL maxima of the leaves without parent that neither the restriction

@@ -320,7 +320,7 @@ def test_launch_config_checks():
         assert N.map_get_launch(ctx)["step_blocks_per_group"] == 7
     finally:
         N.map_destroy(ctx)
-    # a 2-D LF tree of at least 4 leaves per CU takes the CFL maxima in the
+    # batched 2-D LF launches over at least 4 leaves per CU take the CFL maxima in the
     # update by default; 0 turns it off, and -1 restores the rule
     wk = W.kh_ensemble(nsims=64)
     ctx = N.map_init_blocks(N.make_params(2), wk.sims, wk.keys)
@@ -329,6 +329,11 @@ def test_launch_config_checks():
         N.map_set_launch_config(ctx, {"cfl_in_update": 0})
         assert N.map_get_launch(ctx)["cfl_in_update_on"] == 0
         N.map_set_launch_config(ctx, {"cfl_in_update": -1})
+        assert N.map_get_launch(ctx)["cfl_in_update_on"] == 1
+        # a launch per block leaves it to the CFL pass unless forced
+        N.map_set_launch_config(ctx, {"mode": N.MAP_LAUNCH_PER_BLOCK})
+        assert N.map_get_launch(ctx)["cfl_in_update_on"] == 0
+        N.map_set_launch_config(ctx, {"cfl_in_update": 1})
         assert N.map_get_launch(ctx)["cfl_in_update_on"] == 1
     finally:
         N.map_destroy(ctx)
