@@ -325,6 +325,18 @@ def time_cycles(sim, steps, graph=True):
     return (time.perf_counter() - t0) / steps
 
 
+def plain_sim(wl, precision):
+    """The per-block ("plain") path: one launch per block and stage.  In 2-D
+    it takes the 7-block, two-wave workgroup shape: a launch holds one block,
+    and that shape runs it with fewer idle waves and no spilled registers
+    (1.32 s against 1.79 s per cycle of the KH ensemble in FP32)."""
+    from paper_1204_5849_amd.sim import Simulation
+    p = Simulation(wl, precision=precision, launch="per_block")
+    if wl.ndim == 2 and wl.scheme != "mmc":
+        p.set_launch_config(step_shape=1)
+    return p
+
+
 def measure_config(key, precision_b, precision_p, steps_b, steps_p, l1_cycles=0,
                    plain_graph=False, batched_only=False):
     """One configuration besides the headline: its batched path (autotuned,
@@ -354,11 +366,12 @@ def measure_config(key, precision_b, precision_p, steps_b, steps_p, l1_cycles=0,
     if batched_only:
         return out
     wp = build_workload(key, precision_p)
-    p = Simulation(wp, precision=precision_p, launch="per_block")
+    p = plain_sim(wp, precision_p)
     p.load_initial()
     tp = time_cycles(p, steps_p, graph=plain_graph)
     out["plain"] = {"precision": precision_p, "value": cells / tp, "ms_per_step": tp * 1e3,
-                    "steps": steps_p, "launch": "one launch per block and stage"}
+                    "steps": steps_p, "launch": "one launch per block and stage",
+                    "launch_config": p.launch_config()}
     out["speedup_batched_vs_plain"] = tp / tb
     del p
     torch.cuda.empty_cache()
@@ -789,7 +802,7 @@ def main():
         log("FP64 plain per-block path on the same workload")
         from paper_1204_5849_amd import workloads as W  # noqa: F401
         wl64 = build_workload(args.workload, "fp64")
-        p = Simulation(wl64, precision="fp64", launch="per_block")
+        p = plain_sim(wl64, "fp64")
         p.load_initial()
         p.advance(1)
         p.sync()
