@@ -65,3 +65,31 @@ def test_autotune_picks_from_its_search_space(dev):
     leaves = w.leaf_mask()
     got = s.state_by_key()
     assert np.array_equal(got[leaves][:, :, 2:-2, 2:-2, 2:-2], u0[leaves][:, :, 2:-2, 2:-2, 2:-2])
+
+
+@pytest.mark.parametrize("poke", ["e0", "nan"])
+def test_cfl_in_update_counts_like_the_cfl_pass(dev, poke):
+    """The 2-D LF update's CFL maxima (map_launch.cfl_in_update) count the
+    cells with p <= 0 and the non-finite cells exactly as the CFL pass does:
+    a cell poked from the host, then cycles whose dt chain through the
+    update, give the same counters, status and state with it on and off."""
+    w = W.orszag_tang(2)
+    got = []
+    for on in (0, 1):
+        s = _sim(w)
+        s.set_launch_config(cfl_in_update=on)
+        assert s.launch_config()["cfl_in_update_on"] == on
+        s.advance(1)
+        s.flags()
+        slot = int(s.slot_of_key[0])
+        if poke == "e0":
+            s.U[slot, 7, 0, 5, 5] = 0.0  # e = 0 -> negative pressure
+        else:
+            s.U[slot, 0, 0, 6, 6] = float("nan")
+        s.advance(3)
+        st, cnt = s.flags()
+        _say(f"poke {poke} cfl_in_update={on}: status {st} counters {list(cnt)}")
+        got.append((st, list(cnt), s.state_by_key()))
+    assert got[0][0] == got[1][0] and got[0][1] == got[1][1]
+    assert got[0][1][2] + got[0][1][3] >= 1
+    assert np.array_equal(got[0][2], got[1][2], equal_nan=True)
