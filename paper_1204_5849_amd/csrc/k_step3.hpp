@@ -12,7 +12,11 @@
 //   * march-axis neighbours (slopes, the half-step flux, the face between
 //     planes, source and resistive differences) stay in the thread's
 //     registers; in-plane neighbours are exchanged through LDS one plane at
-//     a time (state, right face states, face fluxes, eta J);
+//     a time (state, right face states, face fluxes, eta J).  LF takes two
+//     barriers per plane, face states published and face fluxes published,
+//     and writes the state of plane k+1 between the two into the slot of
+//     plane k-1, which has no reader left after the first; the WENO stages
+//     publish plane k behind a third barrier at the top of its iteration;
 //   * the ring of cells just outside the interior (minus its corners) feeds
 //     the block's boundary faces: lanes 0-15 of wave w own the ring side w
 //     (x = -1, x = 16, y = -1, y = 16) and load its cells two planes ahead
@@ -120,6 +124,11 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
     // a plane, ring cell ln on side ln / 16.  WENO (whose ring pass is a few
     // face states, cheaper than moving it): the ring lanes of every wave
     constexpr bool RING1 = SCH == SCH_LF;
+    // LF: two barriers per plane, the next plane published between them;
+    // WENO stages: a third barrier after publishing plane k at the top of
+    // its iteration (the WENO stages measured no faster, with HLLC slower,
+    // in the two-barrier form)
+    constexpr bool TWOB = SCH == SCH_LF;
     const int rsd = ln >> 4, rix = ln & 15;
     const int rex = rsd == 0 ? -1 : (rsd == 1 ? NB : rix);
     const int rey = rsd == 2 ? -1 : (rsd == 3 ? NB : rix);
@@ -203,6 +212,12 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
         auto splane = [&](int k) { return su + ((k + 2) & 1) * SUB; };
         auto rplane = [&](int k) { return sring + ((k + 2) & 1) * (NV * NRING); };
 
+        // LF: planes -2 and -1 in LDS before the march (plane -2: the
+        // interior columns only, read as the z neighbour of plane -1), the
+        // ring of plane 0 in its buffer, outer cells of plane 0 and ring
+        // cells of plane 1 in flight.  WENO: plane -2's interior columns in
+        // LDS, the ring of plane -1 in its buffer, outer cells of plane -1 and
+        // ring cells of plane 0 in flight
         T u0[NV], up[NV], upp[NV], xc[NV];
         {
             T um[NV];
@@ -214,16 +229,42 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
         }
         load(u0, -1);
         load(up, 0);
-        if (isout) {
-            load_x(xc, -1);
-        } else if (isring) {
-            T r1[NV];
-            load_x(r1, -1);
-            T *rb = rplane(-1);
+        if constexpr (TWOB) {
+            T *s = splane(-1);
 #pragma unroll
             for (int v = 0; v < NV; v++)
-                rb[v * NRING + ri] = r1[v];
-            load_x(xc, 0);
+                s[v * XS3 + q] = u0[v];
+            if (isld) {
+                T r1[NV];
+                load_x(r1, -1);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    s[v * XS3 + xq] = r1[v];
+                if (isring) {
+                    load_x(r1, 0);
+                    T *rb = rplane(0);
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        rb[v * NRING + ri] = r1[v];
+                }
+            }
+            if (isout)
+                load_x(xc, 0);
+            else if (isring)
+                load_x(xc, 1);
+            __syncthreads();
+        } else {
+            if (isout) {
+                load_x(xc, -1);
+            } else if (isring) {
+                T r1[NV];
+                load_x(r1, -1);
+                T *rb = rplane(-1);
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    rb[v * NRING + ri] = r1[v];
+                load_x(xc, 0);
+            }
         }
         // carried to the next plane: Wc = u - (in-plane flux differences)
         // + dt (sources + in-plane resistive terms), the flux of the face
@@ -324,32 +365,39 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
         for (int k = -1; k <= NB; ++k) {
             const bool kI = k >= 0 && k < NB;
             T *const sc = splane(k);
-            const T *const sm = splane(k - 1);
-            // ---- (A) publish plane k; prefetch plane k+2 (interior, ring)
-            //      and k+1 (outer cells)
-#pragma unroll
-            for (int v = 0; v < NV; v++)
-                sc[v * XS3 + q] = u0[v];
-            if (isout) {
+            T *const sm = splane(k - 1);
+            if constexpr (TWOB) {
+                // plane k is in LDS (published before the previous plane's
+                // last barrier); prefetch the interior columns of plane k+2
+                if (k + 2 <= NB + 1)
+                    load(upp, k + 2);
+            } else {
+                // ---- (A) publish plane k; prefetch plane k+2 (interior,
+                //      ring) and k+1 (outer cells)
 #pragma unroll
                 for (int v = 0; v < NV; v++)
-                    sc[v * XS3 + xq] = xc[v];
-                if (k + 1 <= NB + 1)
-                    load_x(xc, k + 1);
-            } else if (isring) {
-                const T *rk = rplane(k);
-                T *rn = rplane(k + 1);
+                    sc[v * XS3 + q] = u0[v];
+                if (isout) {
 #pragma unroll
-                for (int v = 0; v < NV; v++) {
-                    sc[v * XS3 + xq] = rk[v * NRING + ri];
-                    rn[v * NRING + ri] = xc[v];
+                    for (int v = 0; v < NV; v++)
+                        sc[v * XS3 + xq] = xc[v];
+                    if (k + 1 <= NB + 1)
+                        load_x(xc, k + 1);
+                } else if (isring) {
+                    const T *rk = rplane(k);
+                    T *rn = rplane(k + 1);
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        sc[v * XS3 + xq] = rk[v * NRING + ri];
+                        rn[v * NRING + ri] = xc[v];
+                    }
+                    if (k + 2 <= NB + 1)
+                        load_x(xc, k + 2);
                 }
                 if (k + 2 <= NB + 1)
-                    load_x(xc, k + 2);
+                    load(upp, k + 2);
+                __syncthreads();
             }
-            if (k + 2 <= NB + 1)
-                load(upp, k + 2);
-            __syncthreads();
 
             // ---- ring pass: the one face state of each ring cell the
             //      interior reads, and its eta J
@@ -526,6 +574,34 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
             if (ringw)
                 __builtin_amdgcn_s_setprio(0);
             __syncthreads();  // (B) face states, their pressures and eta J published
+
+            // ---- LF: publish plane k+1 into the slot of plane k-1, whose
+            //      last readers (ring and interior passes) are behind (B);
+            //      the barrier (D) below orders it before plane k+1's
+            //      passes.  Prefetch the outer cells of plane k+2 and the
+            //      ring cells of plane k+3.
+            if (TWOB && k + 1 <= NB) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    sm[v * XS3 + q] = up[v];
+                if (isout) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        sm[v * XS3 + xq] = xc[v];
+                    if (k + 2 <= NB + 1)
+                        load_x(xc, k + 2);
+                } else if (isring) {
+                    const T *r1 = rplane(k + 1);
+                    T *r2 = rplane(k + 2);
+#pragma unroll
+                    for (int v = 0; v < NV; v++) {
+                        sm[v * XS3 + xq] = r1[v * NRING + ri];
+                        r2[v * NRING + ri] = xc[v];
+                    }
+                    if (k + 3 <= NB + 1)
+                        load_x(xc, k + 3);
+                }
+            }
 
             // ---- fluxes: in-plane faces x+1/2, y+1/2 of the interior cells and
             //      the faces -1/2 (ring waves of the -1 sides).  The flux of a
