@@ -13,7 +13,10 @@
 //     source and resistive differences) stay in the thread's registers;
 //   * x neighbours are exchanged through LDS one row at a time (state, right
 //     face states, face fluxes, eta J); the outer cells x = -2 and x = 17
-//     are only loaded, by the first threads, one row ahead;
+//     are only loaded, by the first threads, one row ahead.  LF takes two
+//     barriers per row, face states published and face fluxes published,
+//     and writes the state of row k+1 between the two into the slot of row
+//     k-1; the WENO stages publish row k behind a third barrier;
 //   * ghost cells are read where the ghost descriptors point (Sec. 4.3): a
 //     same-level neighbour's interior in U_in, with periodic wrap or outflow
 //     clamping, or the block's own prolongated ghost region, so no copy pass
@@ -59,6 +62,10 @@ __global__ void __launch_bounds__(nt_of(BPW), occ_hint<T>(BPW)) k_step2(StepArgs
     constexpr int NXT2 = 2 * BPW;  // load-only cells (x = -2, x = 17) per row
     static_assert(BPW * NCOL2 <= NT2, "one thread per column");
     constexpr int SUB = BPW * NV * XS;
+    // LF: two barriers per row, the next row published between them; WENO
+    // stages: a third barrier after publishing row k at the top of its
+    // iteration (as in the 3-D kernel)
+    constexpr bool TWOB = SCH == SCH_LF;
     __shared__ T su[2 * SUB];             // state of rows k and k-1 (by parity)
     __shared__ T srf[BPW * NV * XS];      // right face states, then fluxes
     __shared__ T spr[BPW * XS];           // pressures of those face states
@@ -200,6 +207,23 @@ __global__ void __launch_bounds__(nt_of(BPW), occ_hint<T>(BPW)) k_step2(StepArgs
         load(u0, -1);
         load(up, 0);
         load_x(xc, -1);
+        if constexpr (TWOB) {
+            // LF: row -1 in LDS before the march, the load-only cell of row 0
+            // in flight
+            T *const s = su + SUB;  // row -1
+            if (lane) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    s[(lb * NV + v) * XS + q] = u0[v];
+            }
+            if (xhas) {
+#pragma unroll
+                for (int v = 0; v < NV; v++)
+                    s[(xlb * NV + v) * XS + xq] = xc[v];
+            }
+            load_x(xc, 0);
+            __syncthreads();
+        }
         // carried to the next row: Wc = u - (x flux difference) + dt (sources
         // + x resistive terms), the flux of the face k-1/2 (the y difference
         // is taken as a difference, so a uniform state stays exactly
@@ -221,35 +245,42 @@ __global__ void __launch_bounds__(nt_of(BPW), occ_hint<T>(BPW)) k_step2(StepArgs
 
         for (int k = -1; k <= NB; ++k) {
             const bool kI = k >= 0 && k < NB;
-            T *const sc = su + ((k + 2) & 1) * SUB;        // row k
-            const T *const sm = su + ((k + 1) & 1) * SUB;  // row k-1
+            T *const sc = su + ((k + 2) & 1) * SUB;  // row k
+            T *const sm = su + ((k + 1) & 1) * SUB;  // row k-1
             auto um = [&](int v) { return sm[(lb * NV + v) * XS + q]; };
-            // ---- (A) publish row k (own column and the load-only cell)
-            if (lane) {
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    sc[(lb * NV + v) * XS + q] = u0[v];
-            }
-            if (xhas) {
-#pragma unroll
-                for (int v = 0; v < NV; v++)
-                    sc[(xlb * NV + v) * XS + xq] = xc[v];
-            }
-            if (k + 2 <= NB + 1)
-                load(upp, k + 2);
-            if (k + 1 <= NB + 1)
-                load_x(xc, k + 1);
             // WENO stage 2: u of the cell finalised in this iteration
             T ubase[SCH == SCH_WENO2 ? NV : 1];
-            if constexpr (SCH == SCH_WENO2) {
-                if (inI && k >= 1 && has) {
-                    const T *b = (const T *)a.Ubase + (size_t)slot * NV * P + (k - 1 + NG) * XS + q;
+            if constexpr (TWOB) {
+                // row k is in LDS (published before the previous row's last
+                // barrier); prefetch the own column's row k+2
+                if (k + 2 <= NB + 1)
+                    load(upp, k + 2);
+            } else {
+                // ---- (A) publish row k (own column and the load-only cell)
+                if (lane) {
 #pragma unroll
                     for (int v = 0; v < NV; v++)
-                        ubase[v] = b[v * P];
+                        sc[(lb * NV + v) * XS + q] = u0[v];
                 }
+                if (xhas) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        sc[(xlb * NV + v) * XS + xq] = xc[v];
+                }
+                if (k + 2 <= NB + 1)
+                    load(upp, k + 2);
+                if (k + 1 <= NB + 1)
+                    load_x(xc, k + 1);
+                if constexpr (SCH == SCH_WENO2) {
+                    if (inI && k >= 1 && has) {
+                        const T *b = (const T *)a.Ubase + (size_t)slot * NV * P + (k - 1 + NG) * XS + q;
+#pragma unroll
+                        for (int v = 0; v < NV; v++)
+                            ubase[v] = b[v * P];
+                    }
+                }
+                __syncthreads();
             }
-            __syncthreads();
 
             T Lin[NV], pLin = T(1), Lm[NV], Rm[NV], fmc[NV];
             T pLm = T(1), pRm = T(1);
@@ -415,6 +446,25 @@ __global__ void __launch_bounds__(nt_of(BPW), occ_hint<T>(BPW)) k_step2(StepArgs
                 }
             }
             __syncthreads();  // (B) right face states, their pressures and eta J published
+
+            // ---- LF: publish row k+1 into the slot of row k-1, whose last
+            //      readers are behind (B); the barrier (D) below orders it
+            //      before row k+1's pass.  Prefetch the load-only cell of
+            //      row k+2.
+            if (TWOB && k + 1 <= NB) {
+                if (lane) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        sm[(lb * NV + v) * XS + q] = up[v];
+                }
+                if (xhas) {
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        sm[(xlb * NV + v) * XS + xq] = xc[v];
+                }
+                if (k + 2 <= NB + 1)
+                    load_x(xc, k + 2);
+            }
 
             // ---- fluxes of the x faces of row k.  The flux of a face replaces
             //      the right state it was formed from, in the slot of the cell
