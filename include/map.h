@@ -328,8 +328,9 @@ map_status map_set_launch_config(map_ctx *ctx, const map_launch *in);
  * workgroup shapes and persistent grids (multiples of the CU count below the
  * work-item count, and one workgroup per item), then the fill copies over
  * the grids, then the restriction over the per-child split, and keeps the
- * fastest of each, a candidate replacing the choice so far only when faster
- * by more than 1 % (map_get_launch reports them); writes grid_step and
+ * fastest of each (one untimed launch, then the best of five), a candidate
+ * replacing the choice so far only when faster by more than 0.5 %
+ * (map_get_launch reports them); writes grid_step and
  * grid_fill to chosen[2] if not NULL.  Synchronises `stream`.  The trial
  * updates (for WENO, first stages) write the shadow state; U's interiors are
  * not changed (the trial restrictions and copies rewrite parent interiors

@@ -960,9 +960,13 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
     map_dt *dt = dptr<map_dt>(c, c->ws.dt);
     if ((st = run_cfl(c, U, nullptr, s)) != MAP_OK)
         return st;
+    // one untimed launch (the candidate's code and data warm), then the
+    // best of five
     auto time_it = [&](auto &&fn) -> float {
+        if (fn() != MAP_OK)
+            return 1e30f;
         float best = 1e30f;
-        for (int r = 0; r < 3; r++) {
+        for (int r = 0; r < 5; r++) {
             hipEventRecord(e0, s);
             if (fn() != MAP_OK)
                 return 1e30f;
@@ -975,9 +979,9 @@ map_status map_autotune(map_ctx *c, void *U, int *chosen, void *stream)
         return best;
     };
     // a candidate replaces the current choice only when it is faster by more
-    // than the run-to-run spread of these timings (1 %), so that near-ties
+    // than the run-to-run spread of these timings (0.5 %), so that near-ties
     // keep the first candidate tried, the simplest shape
-    auto faster = [](float t, float best) { return t < 0.99f * best; };
+    auto faster = [](float t, float best) { return t < 0.995f * best; };
     // persistent grids: multiples of the compute units below the item count,
     // and one workgroup per work item (0)
     auto grids = [&](int nitems) {
