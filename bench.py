@@ -669,8 +669,9 @@ def main():
         print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 5}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU sharding "
-              "of the block list is a design note, not part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library holds every "
+              "block on one device, and sharding the block list over GPUs is not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
