@@ -403,7 +403,8 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
             //      interior reads, and its eta J
             // LF: the wave that runs this plane's ring pass has the most work
             // before the barrier (B); it issues ahead of the other workgroup's
-            // wave on its SIMD until then
+            // wave on its SIMD until then (from the previous plane's barrier
+            // (D) on)
             const bool ringw = RING1 && kI && wv == (k & 3);
             if (ringw)
                 __builtin_amdgcn_s_setprio(2);
@@ -703,6 +704,10 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                 }
             }
             __syncthreads();  // (D) in-plane face fluxes published
+            // LF: the wave that runs the next plane's ring pass takes its
+            // raised priority from here, through this plane's finalisation
+            if (RING1 && k + 1 < NB && wv == ((k + 1) & 3))
+                __builtin_amdgcn_s_setprio(2);
 
             // ---- finalise plane k-1 with the face k-1/2: z flux difference,
             //      z resistive terms, the Runge-Kutta average (WENO stage 2),
