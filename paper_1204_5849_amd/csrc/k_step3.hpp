@@ -604,6 +604,18 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                 }
             }
 
+            // WENO stage 2: u of the cell finalised in this iteration,
+            // requested before the flux phase so that it lands during it
+            T ubase[SCH == SCH_WENO2 ? NV : 1];
+            if constexpr (SCH == SCH_WENO2) {
+                if (k >= 1) {
+                    const T *b = (const T *)a.Ubase + (size_t)slot * NV * P3 + (k - 1 + NG) * XS3 + q;
+#pragma unroll
+                    for (int v = 0; v < NV; v++)
+                        ubase[v] = b[v * P3];
+                }
+            }
+
             // ---- fluxes: in-plane faces x+1/2, y+1/2 of the interior cells and
             //      the faces -1/2 (ring waves of the -1 sides).  The flux of a
             //      face replaces the right state it was formed from, in the
@@ -667,16 +679,6 @@ __global__ void __launch_bounds__(NT3, OCC) k_step3(StepArgs a)
                 }
             }
             const bool dom = k >= 0;
-            // WENO stage 2: u of the cell finalised in this iteration
-            T ubase[SCH == SCH_WENO2 ? NV : 1];
-            if constexpr (SCH == SCH_WENO2) {
-                if (k >= 1) {
-                    const T *b = (const T *)a.Ubase + (size_t)slot * NV * P3 + (k - 1 + NG) * XS3 + q;
-#pragma unroll
-                    for (int v = 0; v < NV; v++)
-                        ubase[v] = b[v * P3];
-                }
-            }
             if (kI) {
                 // fluxes of block faces shared with another level (reflux):
                 // the faces NB-1/2 here, the faces -1/2 in the ring pass
